@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the library caller and the test oracle.
+
+This subpackage holds no arithmetic of the method itself: it builds meshes
+(vertex coordinates and connectivity), reads stored cubature rules, evaluates
+initial-condition functions at coordinates that the caller supplies, and
+defines the workload recipes (mesh size, order, absorbing-layer profile,
+source and probe parameters).  Everything the DG/PML method computes from these
+inputs lives either in the HIP library or, independently, in the oracle.
+"""
+from .configs import CONFIGS, config, gaussian_fields, load_rule, mesh_for  # noqa: F401
+from .mesh import kuhn_box, orient_positive  # noqa: F401

@@ -1,0 +1,99 @@
+"""Workload recipes: synthetic stand-ins for the paper's experiments.
+
+The paper measures on a plane-wave box and a PEC-sphere mesh (Sec. III) that
+are not available; these seeded cube meshes with a six-sided absorbing layer
+stand in for them.  Their PML fraction (70-90% of elements) is close to the
+72% of the paper's Table I workload.
+
+Each recipe is a plain dict:
+
+  N           polynomial order
+  cub_degree  cubature degree (2N in the paper's Sec. III, 2N+2 for c1)
+  mesh        Kuhn box: n (cubes per side), lo, hi, perturb (fraction of h), seed
+  pml         interface box lo/hi, thickness L, sigma_max (per axis), order p,
+              kappa_max
+  alpha       flux upwinding (1 upwind, 0 central)
+  init        Gaussian initial field: component (0..5 = Ex..Hz), center, width
+  source      Gaussian-modulated dipole current (or None):
+              amplitude * sin(2 pi f0 (t-t0)) exp(-((t-t0)/tau)^2)
+              * exp(-|x-center|^2/width^2) * direction
+  probes      probe points [n, 3] (or None)
+  steps       number of LSERK4 steps
+  cfl         dt = cfl / ((N+1)^2 * max_{k,f} Fscale_{k,f})
+"""
+from __future__ import annotations
+
+import copy
+import os
+
+import numpy as np
+
+from .mesh import kuhn_box
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RULE_DIR = os.path.join(HERE, "cubature")
+
+_CUBE8 = [[sx * 0.5, sy * 0.5, sz * 0.5] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
+
+_DIPOLE = {"amplitude": 1.0, "f0": 1.0, "t0": 0.75, "tau": 0.25, "center": [0.0, 0.0, 0.0],
+           "width": 0.15, "direction": [0.0, 0.0, 1.0]}
+
+CFL = 0.75
+
+CONFIGS = {
+    # 384 tets, N=2, quadratic profile sigma_max=20, Gaussian Ez pulse, 100 steps.
+    "c1": {"name": "c1", "N": 2, "cub_degree": 6,
+           "mesh": {"n": 4, "lo": -1.0, "hi": 1.0, "perturb": 0.0, "seed": 0},
+           "pml": {"lo": [-0.5] * 3, "hi": [0.5] * 3, "L": [0.5] * 3, "sigma_max": [20.0] * 3,
+                   "order": 2.0, "kappa_max": 1.0},
+           "alpha": 1.0,
+           "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.2},
+           "source": None, "probes": None, "steps": 100, "cfl": CFL},
+    # 48,000 perturbed tets, N=3, cubic profile sigma_max=30, dipole, 8 probes, 1000 steps.
+    "c2": {"name": "c2", "N": 3, "cub_degree": 6,
+           "mesh": {"n": 20, "lo": -1.5, "hi": 1.5, "perturb": 0.1, "seed": 0},
+           "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [30.0] * 3,
+                   "order": 3.0, "kappa_max": 1.0},
+           "alpha": 1.0, "init": None, "source": _DIPOLE, "probes": _CUBE8, "steps": 1000, "cfl": CFL},
+    # 384,000 perturbed tets, N=4, quadratic profile sigma_max=40, dipole, 2000 steps.
+    "c3": {"name": "c3", "N": 4, "cub_degree": 8,
+           "mesh": {"n": 40, "lo": -1.5, "hi": 1.5, "perturb": 0.1, "seed": 0},
+           "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [40.0] * 3,
+                   "order": 2.0, "kappa_max": 1.0},
+           "alpha": 1.0, "init": None, "source": _DIPOLE, "probes": _CUBE8, "steps": 2000, "cfl": CFL},
+}
+
+
+def config(name: str, **overrides) -> dict:
+    """Deep copy of a recipe with top-level or nested ('mesh.n') overrides."""
+    cfg = copy.deepcopy(CONFIGS[name])
+    for key, val in overrides.items():
+        parts = key.split(".")
+        d = cfg
+        for p in parts[:-1]:
+            d = d[p]
+        d[parts[-1]] = val
+    return cfg
+
+
+def mesh_for(cfg: dict):
+    m = cfg["mesh"]
+    return kuhn_box(m["n"], m["lo"], m["hi"], m.get("perturb", 0.0), m.get("seed", 0))
+
+
+def load_rule(degree: int):
+    """Stored cubature rule of the given degree: (rst [Nq, 3], w [Nq])."""
+    data = np.loadtxt(os.path.join(RULE_DIR, f"tet_deg{degree}.txt"), comments="#")
+    data = np.atleast_2d(data)
+    return np.ascontiguousarray(data[:, :3]), np.ascontiguousarray(data[:, 3])
+
+
+def gaussian_fields(cfg: dict, xnodes: np.ndarray) -> np.ndarray:
+    """Initial state [K, 12, N_p] from node coordinates xnodes [K, N_p, 3]."""
+    K, Np, _ = xnodes.shape
+    q = np.zeros((K, 12, Np))
+    init = cfg.get("init")
+    if init:
+        r2 = np.sum((xnodes - np.asarray(init["center"])) ** 2, axis=-1)
+        q[:, init["component"], :] = np.exp(-r2 / init["width"] ** 2)
+    return q
