@@ -1,0 +1,189 @@
+"""Benchmark: element-DOF updates per second of the WAA SC-PML DGTD step on one GPU.
+
+Workload (the 48,000-tetrahedron configuration): cube [-1.5, 1.5]^3 cut into
+20^3 x 6 tetrahedra with interior vertices perturbed by up to 10% of h (seed 0),
+order N = 3 (N_p = 20), cubature of degree 6, PML of thickness 0.5 with a
+cubic sigma profile (sigma_max = 30), Gaussian-modulated dipole source,
+8 probes recorded every step, upwind flux, PEC outer wall, LSERK4.
+
+A step is one full LSERK4 step: five launches of the fused stage kernel
+(right-hand side of eqs. (26)-(29) with the upwind curl, the weight-adjusted
+inverse mass and the Runge-Kutta update) plus the probe readout.  Fields live
+in HBM before the timed region starts.  The metric is
+K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
+
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)
+
+
+def algorithmic_traffic(d, word: int):
+    """Algorithmic HBM bytes and flops per stage launch, averaged over the five stages.
+
+    Per PML element and stage: read q_in (12 N_p words), read the residual
+    (12 N_p, stages 2-5 only: the first LSERK coefficient is zero), write the
+    residual and q_out (12 N_p each), sigma at the cubature points (3 N_q),
+    geometry (25 words) and the face-node neighbour map (4 N_fp int32).
+    Interior elements move the 6 E,H components only and no sigma.
+    Neighbour traces are re-reads of q_in (cache traffic, not counted).
+    Flops per PML element (one FMA = 2 flops):
+      volume 3*2*6 N_p^2 + lift 2*6*4 N_fp N_p + PML 6*6*2 N_q N_p + flux ~ 40*4 N_fp;
+    interior elements have no PML term.
+    """
+    Np, Nq, Nfp = d.Np, d.Nq, d.Nfp
+    K, Kp = d.K, d.K_pml
+    Ki = K - Kp
+    fixed_pml = (12 * Np * 3 + 3 * Nq + 25) * word + 4 * Nfp * 4
+    fixed_int = (6 * Np * 3 + 25) * word + 4 * Nfp * 4
+    res_pml = 12 * Np * word
+    res_int = 6 * Np * word
+    bytes_per_launch = Kp * (fixed_pml + 0.8 * res_pml) + Ki * (fixed_int + 0.8 * res_int)
+    fl_common = 36 * Np * Np + 48 * Nfp * Np + 160 * Nfp
+    flops_per_launch = Kp * (fl_common + 72 * Nq * Np) + Ki * fl_common
+    return bytes_per_launch, flops_per_launch
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import torch
+
+    from paper_2006_02551_amd import inputs, wdg
+
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+    d = sim.dims
+    q0 = inputs.gaussian_fields(cfg, sim.node_coords())
+    sim.set_fields(q0)
+    sim.set_dipole(cfg["source"])
+    sim.set_probes(cfg["probes"], steps + warmup + 1)
+    dt = cfg["cfl"] * d.dt_unit
+    stream = torch.cuda.current_stream()
+    sim.step(dt, warmup, stream)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(dt, steps, stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    rows = sim.probe_read(steps + warmup + 1)
+    e = sim.energy()
+    word = 8 if precision == wdg.WDG_FP64 else 4
+    b, f = algorithmic_traffic(d, word)
+    launch_ms = ms / (5 * steps)
+    out = {
+        "value": d.K * d.Np * steps / (ms / 1e3),
+        "ms_per_step": ms / steps,
+        "stage_launch_us": launch_ms * 1e3,
+        "bytes_per_launch": b,
+        "flops_per_launch": f,
+        "achieved_gbs": b / (launch_ms / 1e3) / 1e9,
+        "achieved_tflops": f / (launch_ms / 1e3) / 1e12,
+        "energy": e,
+        "probe_rows": int(rows.shape[0]),
+        "dims": {"K": d.K, "K_pml": d.K_pml, "Np": d.Np, "Nq": d.Nq, "nblk": d.nblk},
+    }
+    del sim
+    return out
+
+
+def cpu_baseline(cfg, steps=1):
+    """The FP64 oracle on the host cores for a bounded sample (one LSERK4 step)."""
+    import numpy as np
+
+    from oracle.run import Simulation as OSim
+    from paper_2006_02551_amd import inputs
+
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    osim = OSim(cfg, vx, ev, *rule)
+    osim.set_state(inputs.gaussian_fields(cfg, osim.mesh.x))
+    t0 = time.perf_counter()
+    osim.run(steps)
+    sec = time.perf_counter() - t0
+    K, Np = osim.mesh.K, osim.ref.Np
+    assert np.all(np.isfinite(osim.q))
+    return {"value": K * Np * steps / sec, "unit": "element-DOF updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} LSERK4 step(s) of the 48,000-tet N=3 workload in the NumPy FP64 oracle "
+                      f"({sec:.1f} s; single-threaded einsum; host has {os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the element-partitioned "
+              f"multi-GPU path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2006_02551_amd import inputs, wdg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = inputs.config("c2")
+    print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
+    r64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup)
+    print(f"bench: FP64 {r64['value']:.3e} DOF/s, {r64['ms_per_step']:.3f} ms/step; FP32 next",
+          file=sys.stderr, flush=True)
+    r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup)
+    print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on one step", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg)
+    d = r64["dims"]
+    line = {
+        "metric": "element-DOF updates/s (WADG-PML RHS+LSERK) FP64 vs FP32; adjoint/forward ratio",
+        "value": r64["value"],
+        "unit": "element-DOF updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: 20^3x6=48000 perturbed tets, N=3, Nq=24, cubic PML sigma_max=30, dipole, "
+                               "8 probes, LSERK4", "K": d["K"], "K_pml": d["K_pml"], "N": 3, "Np": d["Np"],
+                   "Nq": d["Nq"], "parallelism": "single GPU"},
+        "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+                 "speedup_vs_fp64": r32["value"] / r64["value"],
+                 "roofline": {"bound": "hbm", "achieved": r32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": r32["achieved_gbs"] / HBM_PEAK_GBS,
+                              "achieved_tflops": r32["achieved_tflops"],
+                              "flop_frac": r32["achieved_tflops"] / FP32_PEAK_TFLOPS}},
+        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel<double,3,false>", "stage_launch_us": r64["stage_launch_us"],
+                     "bytes_per_launch": r64["bytes_per_launch"],
+                     "achieved_tflops": r64["achieved_tflops"],
+                     "flop_frac": r64["achieved_tflops"] / FP64_PEAK_TFLOPS},
+        "adjoint_forward_ratio": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

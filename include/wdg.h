@@ -1,0 +1,214 @@
+/*
+ * wdg.h -- C ABI of the weight-adjusted smoothly-varying SC-PML DGTD library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the semi-discrete Maxwell system with a stretched-
+ * coordinate PML, eqs. (26)-(29) of Chen, Ozakin, Ahmed, Bagci,
+ * "A Memory-efficient Implementation of Perfectly Matched Layer with
+ * Smoothly-varying Coefficients in Discontinuous Galerkin Time-Domain Method"
+ * (Sec. II-A), on affine tetrahedra with nodal Lagrange elements of order N,
+ * the upwind curl operator of eqs. (15)-(17), the weight-adjusted inverse mass
+ * of eq. (21) and the fused operators of eqs. (22)-(25), integrated in time by
+ * the five-stage fourth-order low-storage Runge-Kutta scheme of Carpenter and
+ * Kennedy (the paper leaves the integrator open).
+ *
+ * Conventions (fixed; they define the canonical user layout):
+ *  - units are normalised: eps0 = mu0 = c = 1, vacuum inside elements;
+ *  - reference tetrahedron v0=(-1,-1,-1), v1=(1,-1,-1), v2=(-1,1,-1),
+ *    v3=(-1,-1,1); an element maps v_i to its i-th vertex; tetrahedra with
+ *    negative orientation get their last two vertices swapped;
+ *  - nodes: equispaced lattice r=-1+2a/N, s=-1+2b/N, t=-1+2c/N with
+ *    a+b+c <= N, ordered c outermost, then b, then a;
+ *  - canonical field array: double [K][12][Np] in user element order with
+ *    components Ex Ey Ez Hx Hy Hz PEx PEy PEz PHx PHy PHz; the auxiliary
+ *    components exist only in PML elements (ignored on set, zero on get);
+ *  - a mesh face without a neighbour is a perfect electric conductor wall;
+ *  - PML profile per axis u: with d_u the distance from the interface box
+ *    [pml_lo, pml_hi] into the layer, sigma_u = sigma_max_u (d_u/L_u)^p and
+ *    kappa_u = 1 + (kappa_max - 1)(d_u/L_u)^p (p = 0 means a step);
+ *    an element is a PML element when sigma or kappa differ from vacuum at
+ *    any of its cubature points.
+ *
+ * All functions return WDG_OK (0) or a negative error code; no C++ exception
+ * crosses this boundary.  A context is not thread-safe: use one per host
+ * thread and stream.  Inputs passed by pointer are copied unless stated.
+ */
+#ifndef WDG_H
+#define WDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WDG_OK 0
+#define WDG_EINVAL (-1)     /* bad argument (null pointer, size, order, rule) */
+#define WDG_EMESH (-2)      /* degenerate tetrahedron, non-manifold or non-conforming face */
+#define WDG_ENOMEM (-3)     /* host or device allocation failed */
+#define WDG_EHIP (-4)       /* HIP runtime error (message in wdg_last_error) */
+#define WDG_ESTATE (-5)     /* state buffers not bound, or a host-only context */
+#define WDG_EPROBE (-6)     /* probe point outside the mesh, or probe buffer full */
+#define WDG_ENONFINITE (-7) /* energy readout is not finite */
+
+#define WDG_FP64 0
+#define WDG_FP32 1
+
+/* wdg_method.flags */
+#define WDG_HOST_ONLY 1 /* build the host-side setup only: no device memory, no stepping */
+
+typedef struct wdg_ctx wdg_ctx;
+
+/* Tetrahedral mesh.  vxyz: double [nv][3]; etov: int32 [K][4] (0-based). */
+typedef struct wdg_mesh {
+    int32_t nv;
+    const double* vxyz;
+    int32_t K;
+    const int32_t* etov;
+} wdg_mesh;
+
+/* Discretisation and PML parameters.
+ * N: polynomial order, 1..4.  cub_rst: double [nq][3] reference coordinates,
+ * cub_w: double [nq] weights of a cubature rule on the reference tetrahedron
+ * that is exact to degree >= 2N (eqs. (19)-(20); nq <= 128).
+ * flux_alpha: 1 upwind, 0 central.  precision: WDG_FP64 or WDG_FP32 (the
+ * stepping arithmetic and state; setup is always FP64). */
+typedef struct wdg_method {
+    int32_t N;
+    int32_t nq;
+    const double* cub_rst;
+    const double* cub_w;
+    double flux_alpha;
+    int32_t precision;
+    int32_t flags;
+    double pml_lo[3];
+    double pml_hi[3];
+    double pml_L[3];
+    double sigma_max[3];
+    double profile_order;
+    double kappa_max;
+} wdg_method;
+
+typedef struct wdg_dims_t {
+    int32_t K, K_pml, N, Np, Nfp, Nq;
+    int32_t block;          /* elements per element block (device layout) */
+    int32_t nblk_pml, nblk; /* PML blocks come first */
+    int32_t precision;
+    int32_t has_kappa;
+    int64_t state_bytes; /* bytes of each of the three state buffers */
+    double dt_unit;      /* 1 / ((N+1)^2 max_{k,f} Fscale_{k,f}); dt = cfl * dt_unit */
+    double time;         /* current simulation time */
+    int64_t steps;       /* steps taken since creation / last set_fields */
+} wdg_dims_t;
+
+/* Gaussian-modulated dipole current, added to dE/dt as -J:
+ * J(x,t) = amplitude sin(2 pi f0 (t - t0)) exp(-((t - t0)/tau)^2)
+ *          exp(-|x - center|^2 / width^2) direction.
+ * Nodes where the spatial factor is below 1e-16 are left out. */
+typedef struct wdg_dipole {
+    double amplitude, f0, t0, tau;
+    double center[3];
+    double width;
+    double direction[3];
+} wdg_dipole;
+
+/* Memory accounting (bytes), Sec. II-B: the direct method stores
+ * 15 N_p^2 words per PML element, the weight-adjusted one 15 N_q words per PML
+ * element plus 2 N_p N_q shared words; this library stores sigma (and kappa)
+ * at the cubature points, 3 (6) N_q words per PML element. */
+typedef struct wdg_mem_t {
+    int64_t state;           /* three state buffers (caller-owned) */
+    int64_t geometry;        /* metric terms, normals, Fscale, Jacobians */
+    int64_t connectivity;    /* face-node neighbour map */
+    int64_t coefficients;    /* sigma/kappa at cubature points */
+    int64_t operators;       /* reference operators */
+    int64_t paper_direct;    /* 15 N_p^2 K_pml words of the direct method */
+    int64_t paper_waa;       /* 15 N_q K_pml + 2 N_p N_q words of the paper's WAA storage */
+} wdg_mem_t;
+
+/* Version: major*10000 + minor*100 + patch. */
+int32_t wdg_version(void);
+
+/* Message for an error code. */
+const char* wdg_error_string(int32_t code);
+
+/* Last error message of a context (or of the last failed wdg_create if ctx is NULL). */
+const char* wdg_last_error(const wdg_ctx* ctx);
+
+/* Builds the reference operators (eqs. (14)-(21)), geometry, face matching,
+ * element classification and device layout; uploads them to the current HIP
+ * device unless WDG_HOST_ONLY.  The mesh and method arrays are copied. */
+int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* method, wdg_ctx** out);
+
+/* Releases everything the library allocated.  Bound state buffers are not freed. */
+void wdg_destroy(wdg_ctx* ctx);
+
+int32_t wdg_get_dims(const wdg_ctx* ctx, wdg_dims_t* out);
+
+/* Binds three caller-owned device buffers of dims.state_bytes bytes each
+ * (two ping-pong field buffers and the Runge-Kutta residual).  They must stay
+ * valid until they are rebound or the context is destroyed. */
+int32_t wdg_bind_state(wdg_ctx* ctx, void* q0, void* q1, void* res, int64_t bytes_each);
+
+/* Copies fields in the canonical layout to / from the device (synchronous).
+ * set_fields resets the residual, the step counter and the probe rows; it
+ * keeps the time. */
+int32_t wdg_set_fields(wdg_ctx* ctx, const double* q);
+int32_t wdg_get_fields(wdg_ctx* ctx, double* q);
+/* The Runge-Kutta residual buffer in the canonical layout (after wdg_rhs it
+ * holds the right-hand side). */
+int32_t wdg_get_residual(wdg_ctx* ctx, double* r);
+
+int32_t wdg_set_time(wdg_ctx* ctx, double t);
+
+/* Sets (or, with NULL, removes) the dipole source. */
+int32_t wdg_set_dipole(wdg_ctx* ctx, const wdg_dipole* src);
+
+/* Probe points xyz double [n][3]; each step appends one row of n x 6 values
+ * (Ex..Hz) to a device buffer of `capacity` rows.  n = 0 removes probes. */
+int32_t wdg_set_probes(wdg_ctx* ctx, int32_t n, const double* xyz, int32_t capacity);
+
+/* Copies up to max_rows probe rows (double [rows][n][6]) to out and clears the
+ * buffer (synchronous). */
+int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nrows);
+
+/* Advances nsteps LSERK4 steps of size dt, enqueued on hip_stream (a
+ * hipStream_t; NULL for the default stream), without synchronising.
+ * Returns WDG_EPROBE if the probe buffer would overflow. */
+int32_t wdg_step(wdg_ctx* ctx, double dt, int32_t nsteps, void* hip_stream);
+
+/* Evaluates the right-hand side of eqs. (26)-(29) at time t into the residual
+ * buffer (fields unchanged), enqueued on hip_stream. */
+int32_t wdg_rhs(wdg_ctx* ctx, double t, void* hip_stream);
+
+/* Discrete energy 1/2 sum_k J_k (E^T M E + H^T M H) of the current fields,
+ * accumulated in FP64 (synchronises hip_stream).  WDG_ENONFINITE if not finite. */
+int32_t wdg_energy(wdg_ctx* ctx, double* out, void* hip_stream);
+
+/* Host-side setup readouts (valid also for WDG_HOST_ONLY contexts). */
+/* Physical node coordinates double [K][Np][3], user element order. */
+int32_t wdg_node_coords(const wdg_ctx* ctx, double* xyz);
+
+#define WDG_OP_DR 0   /* [Np][Np]   d l_j / dr at node i            */
+#define WDG_OP_DS 1   /* [Np][Np]                                   */
+#define WDG_OP_DT 2   /* [Np][Np]                                   */
+#define WDG_OP_LIFT 3 /* [Np][4 Nfp] M^{-1} times face mass, eq. (17) */
+#define WDG_OP_VQ 4   /* [Nq][Np]   V_q = V_I V^{-1}, eq. (20)      */
+#define WDG_OP_PQ 5   /* [Np][Nq]   P_q = M^{-1} V_q^T W, eq. (21)  */
+#define WDG_OP_M 6    /* [Np][Np]   reference mass matrix, eq. (14) */
+/* FP64 reference operator `which` (row-major). */
+int32_t wdg_reference_op(const wdg_ctx* ctx, int32_t which, double* out);
+
+/* Per-element setup data in user element order; any pointer may be NULL.
+ * J [K]; Fscale [K][4]; normals [K][4][3]; neighbour element and face
+ * [K][4] (self for a wall); is_pml [K]. */
+int32_t wdg_element_info(const wdg_ctx* ctx, double* J, double* Fscale, double* normals,
+                         int32_t* etoe, int32_t* etof, int32_t* is_pml);
+
+int32_t wdg_memory_report(const wdg_ctx* ctx, wdg_mem_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDG_H */

@@ -1,0 +1,69 @@
+// Device-side parameter blocks and launchers shared by the C ABI and the
+// kernels.  All pointers are device pointers.
+//
+// Blocked device layout (B = 64 element slots per block, PML blocks first):
+//   fields   [nblk][6][Np][B]       E, H        then
+//            [nblk_pml][6][Np][B]   P^E, P^H    (one buffer = both parts)
+//   geometry [nblk][25][B]          rx ry rz sx sy sz tx ty tz, then per face
+//                                   nx ny nz Fscale
+//   nbr      [nblk][4 Nfp][B]       offset of the neighbour's trace value of
+//                                   component 0 inside the E,H part, or the
+//                                   bitwise complement of the own offset at a
+//                                   PEC wall
+//   sigma    [nblk_pml][3][Nq][B]   (kappa likewise when it is not one)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wdg {
+
+constexpr int kBlock = 64;   // element slots per block (one wavefront)
+constexpr int kGeo = 25;     // geometry words per element slot
+constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
+
+struct StageParams {
+    const void* q_in;
+    void* q_out;
+    void* res;
+    const void* geo;
+    const int* nbr;
+    const void* sigma;
+    const void* kappa;
+    const void* DrT;    // [Np][Np], DrT[j][i] = Dr[i][j]
+    const void* DsT;
+    const void* DtT;
+    const void* LIFTT;  // [4 Nfp][Np]
+    const void* Vq;     // [Nq][Np]
+    const void* PqT;    // [Nq][Np], PqT[q][i] = Pq[i][q]
+    const int* fmask;   // [4][Nfp]
+    const int* src_slot;  // [nblk] source slot of a block or -1
+    const void* src;      // [nslot][3][Np][B] J direction times spatial factor
+    int nblk_pml, nblk, Nq;
+    int read_res;         // 0 when the Runge-Kutta coefficient A is zero
+    double rk_a, rk_b, dt, src_g, alpha;
+};
+
+struct ProbeParams {
+    const void* q;
+    const int* slot;       // [n] element slot of each probe
+    const double* w;       // [n][Np] Lagrange weights
+    double* out;           // [n][6] destination row
+    int n;
+};
+
+struct EnergyParams {
+    const void* q;
+    const double* J;      // [nblk][B]
+    const double* M;      // [Np][Np]
+    double* partial;      // [nblk]
+    int nblk;
+};
+
+// Launchers (kernels.hip); return hipError_t as int.
+int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
+int launch_energy(int precision, int N, const EnergyParams& p, double* out, hipStream_t s);
+
+}  // namespace wdg

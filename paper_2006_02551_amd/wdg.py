@@ -1,0 +1,282 @@
+"""Thin ctypes binding of the C ABI in include/wdg.h.
+
+Only argument marshalling happens here: every step of the method runs in the
+HIP library.  Functions keep the C names; ``Simulation`` bundles the calls a
+typical run needs and lets PyTorch own the three device state buffers.
+
+Importing this module loads ``libwdg.so`` from the package directory and raises
+ImportError if it has not been built (``python -m paper_2006_02551_amd.build``).
+
+PyTorch ships its own copy of the HIP runtime.  Two HIP runtimes in one
+process do not share devices, so torch is imported first: the library's
+dependency on libamdhip64.so.7 then resolves to the runtime torch already
+loaded, and device pointers and streams from torch are valid in the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime before the library (see above)
+    import torch  # noqa: F401
+except ImportError:  # host-only use without torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwdg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2006_02551_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+WDG_OK, WDG_EINVAL, WDG_EMESH, WDG_ENOMEM, WDG_EHIP, WDG_ESTATE, WDG_EPROBE, WDG_ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+WDG_FP64, WDG_FP32 = 0, 1
+WDG_HOST_ONLY = 1
+WDG_OP_DR, WDG_OP_DS, WDG_OP_DT, WDG_OP_LIFT, WDG_OP_VQ, WDG_OP_PQ, WDG_OP_M = range(7)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class wdg_mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("vxyz", _dp), ("K", C.c_int32), ("etov", _ip)]
+
+
+class wdg_method(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nq", C.c_int32), ("cub_rst", _dp), ("cub_w", _dp),
+                ("flux_alpha", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32),
+                ("pml_lo", C.c_double * 3), ("pml_hi", C.c_double * 3), ("pml_L", C.c_double * 3),
+                ("sigma_max", C.c_double * 3), ("profile_order", C.c_double), ("kappa_max", C.c_double)]
+
+
+class wdg_dims_t(C.Structure):
+    _fields_ = [("K", C.c_int32), ("K_pml", C.c_int32), ("N", C.c_int32), ("Np", C.c_int32),
+                ("Nfp", C.c_int32), ("Nq", C.c_int32), ("block", C.c_int32), ("nblk_pml", C.c_int32),
+                ("nblk", C.c_int32), ("precision", C.c_int32), ("has_kappa", C.c_int32),
+                ("state_bytes", C.c_int64), ("dt_unit", C.c_double), ("time", C.c_double), ("steps", C.c_int64)]
+
+
+class wdg_dipole(C.Structure):
+    _fields_ = [("amplitude", C.c_double), ("f0", C.c_double), ("t0", C.c_double), ("tau", C.c_double),
+                ("center", C.c_double * 3), ("width", C.c_double), ("direction", C.c_double * 3)]
+
+
+class wdg_mem_t(C.Structure):
+    _fields_ = [("state", C.c_int64), ("geometry", C.c_int64), ("connectivity", C.c_int64),
+                ("coefficients", C.c_int64), ("operators", C.c_int64), ("paper_direct", C.c_int64),
+                ("paper_waa", C.c_int64)]
+
+
+_ctx = C.c_void_p
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+wdg_version = _sig("wdg_version", C.c_int32)
+wdg_error_string = _sig("wdg_error_string", C.c_char_p, C.c_int32)
+wdg_last_error = _sig("wdg_last_error", C.c_char_p, _ctx)
+wdg_create = _sig("wdg_create", C.c_int32, C.POINTER(wdg_mesh), C.POINTER(wdg_method), C.POINTER(_ctx))
+wdg_destroy = _sig("wdg_destroy", None, _ctx)
+wdg_get_dims = _sig("wdg_get_dims", C.c_int32, _ctx, C.POINTER(wdg_dims_t))
+wdg_bind_state = _sig("wdg_bind_state", C.c_int32, _ctx, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64)
+wdg_set_fields = _sig("wdg_set_fields", C.c_int32, _ctx, _dp)
+wdg_get_fields = _sig("wdg_get_fields", C.c_int32, _ctx, _dp)
+wdg_get_residual = _sig("wdg_get_residual", C.c_int32, _ctx, _dp)
+wdg_set_time = _sig("wdg_set_time", C.c_int32, _ctx, C.c_double)
+wdg_set_dipole = _sig("wdg_set_dipole", C.c_int32, _ctx, C.POINTER(wdg_dipole))
+wdg_set_probes = _sig("wdg_set_probes", C.c_int32, _ctx, C.c_int32, _dp, C.c_int32)
+wdg_probe_read = _sig("wdg_probe_read", C.c_int32, _ctx, _dp, C.c_int32, _ip)
+wdg_step = _sig("wdg_step", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
+wdg_rhs = _sig("wdg_rhs", C.c_int32, _ctx, C.c_double, C.c_void_p)
+wdg_energy = _sig("wdg_energy", C.c_int32, _ctx, _dp, C.c_void_p)
+wdg_node_coords = _sig("wdg_node_coords", C.c_int32, _ctx, _dp)
+wdg_reference_op = _sig("wdg_reference_op", C.c_int32, _ctx, C.c_int32, _dp)
+wdg_element_info = _sig("wdg_element_info", C.c_int32, _ctx, _dp, _dp, _dp, _ip, _ip, _ip)
+wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem_t))
+
+
+class WdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _check(rc, ctx=None):
+    if rc != WDG_OK:
+        msg = wdg_last_error(ctx)
+        raise WdgError(rc, (msg or wdg_error_string(rc)).decode() if isinstance(msg, bytes) else str(msg))
+    return rc
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def make_method(N, rule, pml, alpha=1.0, precision=WDG_FP64, flags=0):
+    """Fill a wdg_method; keeps references to the arrays it points into."""
+    rst, w = _f64(rule[0]), _f64(rule[1])
+    m = wdg_method()
+    m.N = int(N)
+    m.nq = len(w)
+    m.cub_rst = _ptr(rst)
+    m.cub_w = _ptr(w)
+    m.flux_alpha = float(alpha)
+    m.precision = int(precision)
+    m.flags = int(flags)
+    pml = pml or {"lo": [-1e30] * 3, "hi": [1e30] * 3, "L": [1.0] * 3, "sigma_max": [0.0] * 3,
+                  "order": 1.0, "kappa_max": 1.0}
+    for i in range(3):
+        m.pml_lo[i] = float(pml["lo"][i])
+        m.pml_hi[i] = float(pml["hi"][i])
+        m.pml_L[i] = float(pml["L"][i])
+        m.sigma_max[i] = float(pml["sigma_max"][i])
+    m.profile_order = float(pml["order"])
+    m.kappa_max = float(pml.get("kappa_max", 1.0))
+    m._keep = (rst, w)
+    return m
+
+
+def make_mesh(vxyz, etov):
+    v = _f64(vxyz)
+    e = np.ascontiguousarray(etov, dtype=np.int32)
+    m = wdg_mesh()
+    m.nv = v.shape[0]
+    m.vxyz = _ptr(v)
+    m.K = e.shape[0]
+    m.etov = _ptr(e, _ip)
+    m._keep = (v, e)
+    return m
+
+
+class Context:
+    """Owns a wdg_ctx; host-only contexts need no GPU."""
+
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, host_only=False):
+        mesh = make_mesh(vxyz, etov)
+        meth = make_method(N, rule, pml, alpha, precision, WDG_HOST_ONLY if host_only else 0)
+        h = _ctx()
+        _check(wdg_create(C.byref(mesh), C.byref(meth), C.byref(h)))
+        self.h = h
+        self.dims = self.get_dims()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and wdg_destroy is not None:
+            wdg_destroy(h)
+            self.h = None
+
+    def get_dims(self):
+        d = wdg_dims_t()
+        _check(wdg_get_dims(self.h, C.byref(d)), self.h)
+        return d
+
+    def node_coords(self):
+        d = self.dims
+        out = np.zeros((d.K, d.Np, 3))
+        _check(wdg_node_coords(self.h, _ptr(out)), self.h)
+        return out
+
+    def reference_op(self, which):
+        d = self.dims
+        shape = {WDG_OP_DR: (d.Np, d.Np), WDG_OP_DS: (d.Np, d.Np), WDG_OP_DT: (d.Np, d.Np),
+                 WDG_OP_LIFT: (d.Np, 4 * d.Nfp), WDG_OP_VQ: (d.Nq, d.Np), WDG_OP_PQ: (d.Np, d.Nq),
+                 WDG_OP_M: (d.Np, d.Np)}[which]
+        out = np.zeros(shape)
+        _check(wdg_reference_op(self.h, which, _ptr(out)), self.h)
+        return out
+
+    def element_info(self):
+        K = self.dims.K
+        J, Fs, nrm = np.zeros(K), np.zeros((K, 4)), np.zeros((K, 4, 3))
+        etoe, etof, ispml = (np.zeros((K, 4), np.int32), np.zeros((K, 4), np.int32), np.zeros(K, np.int32))
+        _check(wdg_element_info(self.h, _ptr(J), _ptr(Fs), _ptr(nrm), _ptr(etoe, _ip), _ptr(etof, _ip),
+                                _ptr(ispml, _ip)), self.h)
+        return {"J": J, "Fscale": Fs, "normals": nrm, "etoe": etoe, "etof": etof, "is_pml": ispml.astype(bool)}
+
+    def memory_report(self):
+        m = wdg_mem_t()
+        _check(wdg_memory_report(self.h, C.byref(m)), self.h)
+        return {k: getattr(m, k) for k, _ in wdg_mem_t._fields_}
+
+
+class Simulation(Context):
+    """A device context whose three state buffers are PyTorch CUDA (HIP) tensors."""
+
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, device="cuda"):
+        super().__init__(vxyz, etov, N, rule, pml, alpha, precision, host_only=False)
+        nbytes = self.dims.state_bytes
+        self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=device) for _ in range(3)]
+        _check(wdg_bind_state(self.h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
+                              C.c_void_p(self.bufs[2].data_ptr()), nbytes), self.h)
+        self.nprobe = 0
+
+    @staticmethod
+    def _stream(stream):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return C.c_void_p(stream.cuda_stream)
+
+    def set_fields(self, q):
+        q = _f64(q)
+        d = self.dims
+        assert q.shape == (d.K, 12, d.Np)
+        _check(wdg_set_fields(self.h, _ptr(q)), self.h)
+
+    def get_fields(self):
+        d = self.dims
+        out = np.zeros((d.K, 12, d.Np))
+        _check(wdg_get_fields(self.h, _ptr(out)), self.h)
+        return out
+
+    def get_residual(self):
+        d = self.dims
+        out = np.zeros((d.K, 12, d.Np))
+        _check(wdg_get_residual(self.h, _ptr(out)), self.h)
+        return out
+
+    def set_time(self, t):
+        _check(wdg_set_time(self.h, float(t)), self.h)
+
+    def set_dipole(self, src):
+        if src is None:
+            _check(wdg_set_dipole(self.h, None), self.h)
+            return
+        d = wdg_dipole()
+        d.amplitude, d.f0, d.t0, d.tau, d.width = (float(src[k]) for k in ("amplitude", "f0", "t0", "tau", "width"))
+        for i in range(3):
+            d.center[i] = float(src["center"][i])
+            d.direction[i] = float(src["direction"][i])
+        _check(wdg_set_dipole(self.h, C.byref(d)), self.h)
+
+    def set_probes(self, xyz, capacity):
+        xyz = _f64(xyz).reshape(-1, 3)
+        _check(wdg_set_probes(self.h, len(xyz), _ptr(xyz), int(capacity)), self.h)
+        self.nprobe = len(xyz)
+
+    def probe_read(self, max_rows):
+        out = np.zeros((max(int(max_rows), 1), max(self.nprobe, 1), 6))
+        n = C.c_int32(0)
+        _check(wdg_probe_read(self.h, _ptr(out), int(max_rows), C.byref(n)), self.h)
+        return out[:n.value, :self.nprobe]
+
+    def step(self, dt, nsteps, stream=None):
+        _check(wdg_step(self.h, float(dt), int(nsteps), self._stream(stream)), self.h)
+
+    def rhs(self, t, stream=None):
+        _check(wdg_rhs(self.h, float(t), self._stream(stream)), self.h)
+
+    def energy(self, stream=None):
+        e = C.c_double(0.0)
+        _check(wdg_energy(self.h, C.byref(e), self._stream(stream)), self.h)
+        return e.value
