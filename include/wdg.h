@@ -99,6 +99,7 @@ typedef struct wdg_dims_t {
     double dt_unit;      /* 1 / ((N+1)^2 max_{k,f} Fscale_{k,f}); dt = cfl * dt_unit */
     double time;         /* current simulation time */
     int64_t steps;       /* steps taken since creation / last set_fields */
+    int32_t kernel;      /* active stage-kernel variant (WDG_KERNEL_*) */
 } wdg_dims_t;
 
 /* Gaussian-modulated dipole current, added to dE/dt as -J:
@@ -171,6 +172,21 @@ int32_t wdg_set_probes(wdg_ctx* ctx, int32_t n, const double* xyz, int32_t capac
 /* Copies up to max_rows probe rows (double [rows][n][6]) to out and clears the
  * buffer (synchronous). */
 int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nrows);
+
+/* Stage-kernel variants.  Both compute the same stage; they differ in how
+ * the small dense products are executed.
+ *   WDG_KERNEL_SCALAR: one wavefront per field component and 64 elements,
+ *     reference operators as scalar FMA operands (any order and rule size);
+ *   WDG_KERNEL_MFMA: one wavefront per 16 elements, products on the matrix
+ *     cores (the order / cubature sizes listed at wdg_set_kernel).
+ * wdg_create selects MFMA when it is available. */
+#define WDG_KERNEL_AUTO 0
+#define WDG_KERNEL_SCALAR 1
+#define WDG_KERNEL_MFMA 2
+
+/* Selects the stage-kernel variant; WDG_EINVAL if MFMA is not available for
+ * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64). */
+int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
 
 /* Advances nsteps LSERK4 steps of size dt, enqueued on hip_stream (a
  * hipStream_t; NULL for the default stream), without synchronising.

@@ -99,6 +99,9 @@ struct wdg_ctx {
     // device setup
     DevBuf geo, nbr, sigma, kappa, ops, fmask, Jk, Mref, partial, scalar_out;
     DevBuf src_slot, src;
+    DevBuf frags;
+    bool mfma_ok = false;
+    int kernel = WDG_KERNEL_SCALAR;
     bool has_src = false;
     wdg_dipole dip{};
     // probes
@@ -222,6 +225,34 @@ void upload_setup(wdg_ctx* c) {
     c->off_Vq = push(R.Vq);
     c->off_PqT = push(transpose(R.Pq, Np, Nq));
     c->ops.upload(to_real(ops, c->precision).data(), ops.size() * c->rsize);
+
+    // MFMA A-operand fragments.  Lane l of fragment (tile p, k-step s) holds
+    // Op[n(16p + l%16)][4s + l/16]; n() is the row permutation that makes MFMA
+    // register v of lane group g hold quantity 16p + 4v + g (the FP64 MFMA
+    // returns row g + 4v in register v, the FP32 MFMA row 4g + v).
+    c->mfma_ok = mfma_supported(R.N, Nq);
+    if (c->mfma_ok) {
+        const int PT = (Np + 15) / 16, SP = (Np + 3) / 4, QT = (Nq + 15) / 16, SQM = 4 * QT, SF = Nfp;
+        const bool f64 = c->precision == WDG_FP64;
+        auto quantity = [&](int r) { const int rr = r % 16; return 16 * (r / 16) + (f64 ? rr : 4 * (rr % 4) + rr / 4); };
+        std::vector<double> fr;
+        auto add = [&](const Mat& X, int rows, int cols, int tiles, int ksteps) {
+            for (int t = 0; t < tiles; ++t)
+                for (int ks = 0; ks < ksteps; ++ks)
+                    for (int l = 0; l < 64; ++l) {
+                        const int row = quantity(16 * t + l % 16), col = 4 * ks + l / 16;
+                        fr.push_back(row < rows && col < cols ? X[static_cast<size_t>(row) * cols + col] : 0.0);
+                    }
+        };
+        add(R.Vq, Nq, Np, QT, SP);
+        add(R.Pq, Np, Nq, PT, SQM);
+        add(R.Dr, Np, Np, PT, SP);
+        add(R.Ds, Np, Np, PT, SP);
+        add(R.Dt, Np, Np, PT, SP);
+        add(R.LIFT, Np, 4 * Nfp, PT, SF);
+        c->frags.upload(to_real(fr, c->precision).data(), fr.size() * c->rsize);
+        c->kernel = WDG_KERNEL_MFMA;
+    }
     c->fmask.upload(R.fmask.data(), R.fmask.size() * sizeof(int));
     c->Mref.upload(R.M.data(), R.M.size() * sizeof(double));
     c->partial.alloc(static_cast<size_t>(nblk) * sizeof(double));
@@ -254,6 +285,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, double rk_a, double
     p.fmask = static_cast<const int*>(c->fmask.p);
     p.src_slot = static_cast<const int*>(c->src_slot.p);
     p.src = c->src.p;
+    p.frags = c->frags.p;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;
@@ -268,7 +300,8 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, double rk_a, double
         const double tt = t - d.t0;
         p.src_g = d.amplitude * std::sin(2.0 * M_PI * d.f0 * tt) * std::exp(-(tt / d.tau) * (tt / d.tau));
     }
-    const int e = launch_stage(c->precision, S.ref.N, S.has_kappa, p, stream);
+    const int e = c->kernel == WDG_KERNEL_MFMA ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, p, stream)
+                                               : launch_stage(c->precision, S.ref.N, S.has_kappa, p, stream);
     if (e != 0) return fail(c, WDG_EHIP, std::string("stage launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
     return WDG_OK;
 }
@@ -360,6 +393,17 @@ int32_t wdg_get_dims(const wdg_ctx* c, wdg_dims_t* o) {
     o->dt_unit = S.dt_unit;
     o->time = c->t;
     o->steps = c->steps;
+    o->kernel = c->kernel;
+    return WDG_OK;
+}
+
+int32_t wdg_set_kernel(wdg_ctx* c, int32_t variant) {
+    if (!c) return WDG_EINVAL;
+    if (c->host_only) return fail(c, WDG_ESTATE, "host-only context");
+    if (variant == WDG_KERNEL_AUTO) variant = c->mfma_ok ? WDG_KERNEL_MFMA : WDG_KERNEL_SCALAR;
+    if (variant == WDG_KERNEL_MFMA && !c->mfma_ok) return fail(c, WDG_EINVAL, "no MFMA kernel for this order and rule size");
+    if (variant != WDG_KERNEL_MFMA && variant != WDG_KERNEL_SCALAR) return fail(c, WDG_EINVAL, "unknown kernel variant");
+    c->kernel = variant;
     return WDG_OK;
 }
 

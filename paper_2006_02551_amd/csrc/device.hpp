@@ -22,6 +22,7 @@ namespace wdg {
 constexpr int kBlock = 64;   // element slots per block (one wavefront)
 constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
+constexpr int kMfmaThreads = 4 * 64;  // MFMA kernel: one wavefront per 16-element tile
 
 struct StageParams {
     const void* q_in;
@@ -40,6 +41,7 @@ struct StageParams {
     const int* fmask;   // [4][Nfp]
     const int* src_slot;  // [nblk] source slot of a block or -1
     const void* src;      // [nslot][3][Np][B] J direction times spatial factor
+    const void* frags;    // MFMA kernel: operator A fragments (V_q, P_q, D_r, D_s, D_t, LIFT)
     int nblk_pml, nblk, Nq;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
@@ -61,8 +63,10 @@ struct EnergyParams {
     int nblk;
 };
 
-// Launchers (kernels.hip); return hipError_t as int.
+// Launchers (kernels.hip, kernels_mfma.hip); return hipError_t as int.
 int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+bool mfma_supported(int N, int Nq);
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
 int launch_energy(int precision, int N, const EnergyParams& p, double* out, hipStream_t s);
 

@@ -35,6 +35,7 @@ WDG_OK, WDG_EINVAL, WDG_EMESH, WDG_ENOMEM, WDG_EHIP, WDG_ESTATE, WDG_EPROBE, WDG
 WDG_FP64, WDG_FP32 = 0, 1
 WDG_HOST_ONLY = 1
 WDG_OP_DR, WDG_OP_DS, WDG_OP_DT, WDG_OP_LIFT, WDG_OP_VQ, WDG_OP_PQ, WDG_OP_M = range(7)
+WDG_KERNEL_AUTO, WDG_KERNEL_SCALAR, WDG_KERNEL_MFMA = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -55,7 +56,8 @@ class wdg_dims_t(C.Structure):
     _fields_ = [("K", C.c_int32), ("K_pml", C.c_int32), ("N", C.c_int32), ("Np", C.c_int32),
                 ("Nfp", C.c_int32), ("Nq", C.c_int32), ("block", C.c_int32), ("nblk_pml", C.c_int32),
                 ("nblk", C.c_int32), ("precision", C.c_int32), ("has_kappa", C.c_int32),
-                ("state_bytes", C.c_int64), ("dt_unit", C.c_double), ("time", C.c_double), ("steps", C.c_int64)]
+                ("state_bytes", C.c_int64), ("dt_unit", C.c_double), ("time", C.c_double), ("steps", C.c_int64),
+                ("kernel", C.c_int32)]
 
 
 class wdg_dipole(C.Structure):
@@ -93,6 +95,7 @@ wdg_set_time = _sig("wdg_set_time", C.c_int32, _ctx, C.c_double)
 wdg_set_dipole = _sig("wdg_set_dipole", C.c_int32, _ctx, C.POINTER(wdg_dipole))
 wdg_set_probes = _sig("wdg_set_probes", C.c_int32, _ctx, C.c_int32, _dp, C.c_int32)
 wdg_probe_read = _sig("wdg_probe_read", C.c_int32, _ctx, _dp, C.c_int32, _ip)
+wdg_set_kernel = _sig("wdg_set_kernel", C.c_int32, _ctx, C.c_int32)
 wdg_step = _sig("wdg_step", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
 wdg_rhs = _sig("wdg_rhs", C.c_int32, _ctx, C.c_double, C.c_void_p)
 wdg_energy = _sig("wdg_energy", C.c_int32, _ctx, _dp, C.c_void_p)
@@ -269,6 +272,10 @@ class Simulation(Context):
         n = C.c_int32(0)
         _check(wdg_probe_read(self.h, _ptr(out), int(max_rows), C.byref(n)), self.h)
         return out[:n.value, :self.nprobe]
+
+    def set_kernel(self, variant):
+        _check(wdg_set_kernel(self.h, int(variant)), self.h)
+        self.dims = self.get_dims()
 
     def step(self, dt, nsteps, stream=None):
         _check(wdg_step(self.h, float(dt), int(nsteps), self._stream(stream)), self.h)

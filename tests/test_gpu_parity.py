@@ -27,11 +27,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _pair(wdg, cfg, precision=0, init="gaussian", seed=0):
+KERNELS = [0, 1]  # WDG_KERNEL_AUTO (matrix cores where available), WDG_KERNEL_SCALAR
+
+
+def _pair(wdg, cfg, precision=0, init="gaussian", seed=0, kernel=0):
     from oracle.run import Simulation as OSim
     vx, ev = inputs.mesh_for(cfg)
     rule = inputs.load_rule(cfg["cub_degree"])
     sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+    sim.set_kernel(kernel)
     osim = OSim(cfg, vx, ev, *rule)
     if init == "gaussian":
         q0 = inputs.gaussian_fields(cfg, osim.mesh.x)
@@ -62,11 +66,14 @@ RHS_CASES = [
 ]
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name,over", RHS_CASES, ids=[str(i) for i in range(len(RHS_CASES))])
-def test_rhs_parity_fp64(wdg, name, over):
+def test_rhs_parity_fp64(wdg, name, over, kernel):
     cfg = inputs.config(name, **over)
-    _say(f"rhs parity {name} {over}")
-    sim, osim = _pair(wdg, cfg, init="random", seed=3)
+    _say(f"rhs parity {name} {over} kernel {kernel}")
+    sim, osim = _pair(wdg, cfg, init="random", seed=3, kernel=kernel)
+    if kernel == 0:
+        assert sim.dims.kernel == wdg.WDG_KERNEL_MFMA
     t = 0.61
     sim.rhs(t)
     got = sim.get_residual()
@@ -77,10 +84,11 @@ def test_rhs_parity_fp64(wdg, name, over):
     assert np.array_equal(sim.get_fields(), osim.q)
 
 
-def test_c1_100_steps_fp64(wdg):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_c1_100_steps_fp64(wdg, kernel):
     cfg = inputs.config("c1")
-    _say("c1 100 steps fp64")
-    sim, osim = _pair(wdg, cfg)
+    _say(f"c1 100 steps fp64 kernel {kernel}")
+    sim, osim = _pair(wdg, cfg, kernel=kernel)
     e0 = sim.energy()
     assert abs(e0 - osim.energy()) <= 1e-13 * e0
     sim.step(osim.dt, 100)
@@ -111,11 +119,13 @@ def test_c2_small_probes_fp64(wdg):
     assert np.max(np.abs(osim.q[:, :6])) > 0  # the source has radiated
 
 
-@pytest.mark.parametrize("name,over,steps", [("c1", {}, 100), ("c2", {"mesh.n": 6}, 40)])
-def test_fp32_against_fp64_oracle(wdg, name, over, steps):
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,over,steps", [("c1", {}, 100), ("c2", {"mesh.n": 6}, 40),
+                                             ("c1", {"N": 4, "cub_degree": 8, "mesh.n": 2}, 30)])
+def test_fp32_against_fp64_oracle(wdg, name, over, steps, kernel):
     cfg = inputs.config(name, **over)
-    _say(f"fp32 {name} {over}")
-    sim, osim = _pair(wdg, cfg, precision=1)
+    _say(f"fp32 {name} {over} kernel {kernel}")
+    sim, osim = _pair(wdg, cfg, precision=1, kernel=kernel)
     sim.step(osim.dt, steps)
     osim.run(steps)
     q = sim.get_fields()
@@ -124,12 +134,13 @@ def test_fp32_against_fp64_oracle(wdg, name, over, steps):
     assert err <= 1e-5
 
 
-def test_c2_full_size_rhs_sampled(wdg):
-    # BASELINE-size mesh (48,000 tets, N=3) in the launch configuration the benchmark times;
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 2e-5)])
+def test_c2_full_size_rhs_sampled(wdg, precision, tol):
+    # The 48,000-tet N=3 mesh in the launch configuration the benchmark times;
     # the oracle evaluates the right-hand side of a sample of elements only.
     cfg = inputs.config("c2")
-    _say("c2 full size sampled rhs fp64")
-    sim, osim = _pair(wdg, cfg, init="random", seed=11)
+    _say(f"c2 full size sampled rhs precision {precision}")
+    sim, osim = _pair(wdg, cfg, init="random", seed=11, precision=precision)
     t = 0.9
     sim.rhs(t)
     got = sim.get_residual()
@@ -138,7 +149,20 @@ def test_c2_full_size_rhs_sampled(wdg):
                                    np.nonzero(~osim.op.is_pml)[0][:50], [0, osim.mesh.K - 1]]))
     ref = osim.op.rhs(osim.q, t, el=el)
     scale = np.max(np.abs(ref))
-    assert np.max(np.abs(got[el] - ref)) <= 1e-12 * scale
+    assert np.max(np.abs(got[el] - ref)) <= tol * scale
+
+
+def test_kernels_agree(wdg):
+    # the two stage-kernel variants compute the same stage (to FP64 rounding)
+    cfg = inputs.config("c2", **{"mesh.n": 5})
+    _say("kernel variants agree")
+    sim, osim = _pair(wdg, cfg, init="random", seed=2, kernel=1)
+    sim.rhs(0.7)
+    a = sim.get_residual()
+    sim.set_kernel(2)
+    sim.rhs(0.7)
+    b = sim.get_residual()
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
 
 
 def test_determinism_and_restart(wdg):
