@@ -22,7 +22,7 @@ namespace wdg {
 constexpr int kBlock = 64;   // element slots per block (one wavefront)
 constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
-constexpr int kMfmaThreads = 4 * 64;  // MFMA kernel: one wavefront per 16-element tile
+constexpr int kMfmaThreads = 6 * 64;  // MFMA kernel: one wavefront per component of a 16-element tile
 
 struct StageParams {
     const void* q_in;
