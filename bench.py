@@ -82,6 +82,7 @@ def run_gpu(cfg, precision, steps, warmup):
     ms = start.elapsed_time(stop)
     rows = sim.probe_read(steps + warmup + 1)
     e = sim.energy()
+    kernel = {wdg.WDG_KERNEL_MFMA: "stage_mfma_kernel", wdg.WDG_KERNEL_SCALAR: "stage_kernel"}[sim.get_dims().kernel]
     word = 8 if precision == wdg.WDG_FP64 else 4
     b, f = algorithmic_traffic(d, word)
     launch_ms = ms / (5 * steps)
@@ -95,14 +96,15 @@ def run_gpu(cfg, precision, steps, warmup):
         "achieved_tflops": f / (launch_ms / 1e3) / 1e12,
         "energy": e,
         "probe_rows": int(rows.shape[0]),
-        "dims": {"K": d.K, "K_pml": d.K_pml, "Np": d.Np, "Nq": d.Nq, "nblk": d.nblk},
+        "kernel": f"{kernel}<{'double' if word == 8 else 'float'},N={d.N},Nq={d.Nq}>",
+        "dims": {"K": d.K, "K_pml": d.K_pml, "Np": d.Np, "Nq": d.Nq, "nblk": d.nblk, "N": d.N},
     }
     del sim
     return out
 
 
-def cpu_baseline(cfg, steps=1):
-    """The FP64 oracle on the host cores for a bounded sample (one LSERK4 step)."""
+def cpu_baseline(cfg, steps=3):
+    """The FP64 oracle on the host cores for a bounded sample (three LSERK4 steps, about 15 s)."""
     import numpy as np
 
     from oracle.run import Simulation as OSim
@@ -148,7 +150,7 @@ def main():
     print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on one step", file=sys.stderr, flush=True)
+        print("bench: timing the CPU oracle on three steps", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg)
     d = r64["dims"]
     line = {
@@ -167,7 +169,7 @@ def main():
         "config": {"workload": "c2: 20^3x6=48000 perturbed tets, N=3, Nq=24, cubic PML sigma_max=30, dipole, "
                                "8 probes, LSERK4", "K": d["K"], "K_pml": d["K_pml"], "N": 3, "Np": d["Np"],
                    "Nq": d["Nq"], "parallelism": "single GPU"},
-        "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+        "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32", "kernel": r32["kernel"],
                  "speedup_vs_fp64": r32["value"] / r64["value"],
                  "roofline": {"bound": "hbm", "achieved": r32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": r32["achieved_gbs"] / HBM_PEAK_GBS,
@@ -175,7 +177,7 @@ def main():
                               "flop_frac": r32["achieved_tflops"] / FP32_PEAK_TFLOPS}},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage_kernel<double,3,false>", "stage_launch_us": r64["stage_launch_us"],
+                     "kernel": r64["kernel"], "stage_launch_us": r64["stage_launch_us"],
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "achieved_tflops": r64["achieved_tflops"],
                      "flop_frac": r64["achieved_tflops"] / FP64_PEAK_TFLOPS},

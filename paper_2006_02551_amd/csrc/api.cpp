@@ -250,6 +250,9 @@ void upload_setup(wdg_ctx* c) {
         add(R.Ds, Np, Np, PT, SP);
         add(R.Dt, Np, Np, PT, SP);
         add(R.LIFT, Np, 4 * Nfp, PT, SF);
+        // padded to whole 1 KiB chunks (the kernel copies it with 16-byte direct loads into LDS)
+        const int nfrag = static_cast<int>(fr.size() / 64);
+        fr.resize(static_cast<size_t>(frag_chunks(nfrag, static_cast<int>(c->rsize))) * 1024 / c->rsize, 0.0);
         c->frags.upload(to_real(fr, c->precision).data(), fr.size() * c->rsize);
         c->kernel = WDG_KERNEL_MFMA;
     }

@@ -24,6 +24,9 @@ constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
 constexpr int kMfmaThreads = 6 * 64;  // MFMA kernel: one wavefront per component of a 16-element tile
 
+// Number of 1 KiB chunks that hold nfrag MFMA operand fragments of 64 words.
+constexpr int frag_chunks(int nfrag, int word_bytes) { return (nfrag * 64 * word_bytes + 1023) / 1024; }
+
 struct StageParams {
     const void* q_in;
     void* q_out;

@@ -27,12 +27,12 @@
 // 4 g + v for the FP32 MFMA; the host applies the matching permutation.
 //
 // Per PML tile, wavefront u (f = E or H, P its auxiliary field):
+//   B. R = LIFT (Fscale * upwind flux), flux read from LDS in B layout
+//   C. R += D_r G_r + D_s G_s + D_t G_t, G_d = metric-weighted components
 //   A. VF = V_q f_u, VP = V_q P_u; t1 = b VF + c VP, t2 = kappa^-1 VF - d VP
 //      (eq. (9) at the cubature points); rhs_P = P_q t2 (then its LSERK
-//      update); R_u = -P_q t1
-//   B. R += LIFT (Fscale * upwind flux), flux read from LDS in B layout
-//   C. R_u += D_r G_r + D_s G_s + D_t G_t, G_d = metric-weighted components
-//   D. rhs_u = P_q a^-1 V_q R_u (PML tiles), then the LSERK update.
+//      update); R -= P_q t1
+//   D. rhs_u = P_q a^-1 V_q R (PML tiles), then the LSERK update.
 #include "device.hpp"
 
 namespace wdg {
@@ -93,9 +93,9 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     constexpr int OFF_L = OFF_D + 3 * PT * SP;
     constexpr int NFRAG = OFF_L + PT * SF;
     constexpr int EHS = 6 * Np * B;
-    constexpr int FIT = (NF * 16 + kMfmaThreads - 1) / kMfmaThreads;    // flux items per thread
-    constexpr int CIT = (NFRAG * 64 + kMfmaThreads - 1) / kMfmaThreads;  // fragment words per thread
-    __shared__ real fr[NFRAG * 64];
+    constexpr int FIT = (NF * 16 + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread
+    constexpr int NCHUNK = frag_chunks(NFRAG, sizeof(real));          // 1 KiB chunks of fragments
+    __shared__ __attribute__((aligned(16))) real fr[NCHUNK * 1024 / sizeof(real)];
     __shared__ real fl[6 * NF * 16];  // flux [component][face node][element of the tile]
 
     const int tid = static_cast<int>(threadIdx.x);
@@ -118,16 +118,14 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     const real* __restrict__ geo = geo0 + j;
     const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
 
-    // ---- issue every load that does not depend on the flux before the barrier
-    real fcp[CIT];
+    // ---- operators to LDS by direct global->LDS loads (16 bytes per lane, 1 KiB per wavefront)
     {
-        const real* __restrict__ src = static_cast<const real*>(p.frags);
-#pragma unroll
-        for (int it = 0; it < CIT; ++it) {
-            const int i = tid + it * kMfmaThreads;
-            fcp[it] = (i < NFRAG * 64) ? src[i] : real(0);
-        }
+        const char* __restrict__ src = static_cast<const char*>(p.frags);
+        char* dst = reinterpret_cast<char*>(fr);
+        for (int c = u; c < NCHUNK; c += 6)
+            __builtin_amdgcn_global_load_lds(src + c * 1024 + lane * 16, dst + c * 1024, 16, 0, 0);
     }
+    // ---- issue every load that does not depend on the flux before the barrier
     real bf[SP], bp[SP], xb[SP], xc[SP];
     const int fo = (u < 3) ? 3 : 0;
 #pragma unroll
@@ -192,11 +190,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
             f[5 * NF * 16] = hs * ((nx * dEy - ny * dEx) + alpha * (nz * ndH - dHz));
         }
     }
-#pragma unroll
-    for (int it = 0; it < CIT; ++it) {
-        const int i = tid + it * kMfmaThreads;
-        if (i < NFRAG * 64) fr[i] = fcp[it];
-    }
+    __builtin_amdgcn_s_waitcnt(0);  // the direct loads into LDS have landed
     __syncthreads();
 
     const int Nq = p.Nq;
@@ -210,6 +204,43 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     v4 R[PT];
 #pragma unroll
     for (int t = 0; t < PT; ++t) R[t] = v4{0, 0, 0, 0};
+
+    // ---- B. lift of the flux of component u (eqs. (15), (17))
+#pragma unroll
+    for (int s = 0; s < SF; ++s) {
+        const real b = fl[(u * NF + 4 * s + g) * 16 + j];
+#pragma unroll
+        for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L + t * SF + s), b, R[t]);
+    }
+
+    // ---- C. volume curl: +curl H (E components), -curl E (H components)
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+        const real gr = sgn * (mrb * xc[s] - mrc * xb[s]);
+        const real gs = sgn * (msb * xc[s] - msc * xb[s]);
+        const real gt = sgn * (mtb * xc[s] - mtc * xb[s]);
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            R[t] = M::run(frag(OFF_D + (0 * PT + t) * SP + s), gr, R[t]);
+            R[t] = M::run(frag(OFF_D + (1 * PT + t) * SP + s), gs, R[t]);
+            R[t] = M::run(frag(OFF_D + (2 * PT + t) * SP + s), gt, R[t]);
+        }
+    }
+
+    // residual and field of component u for the final update, issued before the products
+    real rold[PT][4], qold[PT][4];
+    {
+        const size_t eb = static_cast<size_t>(blk) * EHS + e;
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int node = 16 * t + 4 * v + g;
+                const size_t idx = eb + static_cast<size_t>(u * Np + (node < Np ? node : 0)) * B;
+                rold[t][v] = read_res ? rs[idx] : real(0);
+                qold[t][v] = qin[idx];
+            }
+    }
 
     // ---- A. PML terms at the cubature points (eqs. (26)-(29))
     if (pml) {
@@ -309,43 +340,6 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                     qo[idx] = qold[t][v] + rkB * r;
                 }
             }
-    }
-
-    // residual and field of component u for the final update, issued before the products
-    real rold[PT][4], qold[PT][4];
-    {
-        const size_t eb = static_cast<size_t>(blk) * EHS + e;
-#pragma unroll
-        for (int t = 0; t < PT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int node = 16 * t + 4 * v + g;
-                const size_t idx = eb + static_cast<size_t>(u * Np + (node < Np ? node : 0)) * B;
-                rold[t][v] = read_res ? rs[idx] : real(0);
-                qold[t][v] = qin[idx];
-            }
-    }
-
-    // ---- B. lift of the flux of component u (eqs. (15), (17))
-#pragma unroll
-    for (int s = 0; s < SF; ++s) {
-        const real b = fl[(u * NF + 4 * s + g) * 16 + j];
-#pragma unroll
-        for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L + t * SF + s), b, R[t]);
-    }
-
-    // ---- C. volume curl: +curl H (E components), -curl E (H components)
-#pragma unroll
-    for (int s = 0; s < SP; ++s) {
-        const real gr = sgn * (mrb * xc[s] - mrc * xb[s]);
-        const real gs = sgn * (msb * xc[s] - msc * xb[s]);
-        const real gt = sgn * (mtb * xc[s] - mtc * xb[s]);
-#pragma unroll
-        for (int t = 0; t < PT; ++t) {
-            R[t] = M::run(frag(OFF_D + (0 * PT + t) * SP + s), gr, R[t]);
-            R[t] = M::run(frag(OFF_D + (1 * PT + t) * SP + s), gs, R[t]);
-            R[t] = M::run(frag(OFF_D + (2 * PT + t) * SP + s), gt, R[t]);
-        }
     }
 
     // ---- dipole source on the electric components
