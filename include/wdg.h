@@ -185,7 +185,8 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
 #define WDG_KERNEL_MFMA 2
 
 /* Selects the stage-kernel variant; WDG_EINVAL if MFMA is not available for
- * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64). */
+ * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64,
+ * FP32 only). */
 int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
 
 /* Advances nsteps LSERK4 steps of size dt, enqueued on hip_stream (a

@@ -230,7 +230,7 @@ void upload_setup(wdg_ctx* c) {
     // Op[n(16p + l%16)][4s + l/16]; n() is the row permutation that makes MFMA
     // register v of lane group g hold quantity 16p + 4v + g (the FP64 MFMA
     // returns row g + 4v in register v, the FP32 MFMA row 4g + v).
-    c->mfma_ok = mfma_supported(R.N, Nq);
+    c->mfma_ok = mfma_supported(R.N, Nq, c->precision);
     if (c->mfma_ok) {
         const int PT = (Np + 15) / 16, SP = (Np + 3) / 4, QT = (Nq + 15) / 16, SQM = 4 * QT, SF = Nfp;
         const bool f64 = c->precision == WDG_FP64;

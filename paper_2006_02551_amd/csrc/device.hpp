@@ -69,7 +69,7 @@ struct EnergyParams {
 // Launchers (kernels.hip, kernels_mfma.hip); return hipError_t as int.
 int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
 int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
-bool mfma_supported(int N, int Nq);
+bool mfma_supported(int N, int Nq, int precision);
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
 int launch_energy(int precision, int N, const EnergyParams& p, double* out, hipStream_t s);
 

@@ -77,94 +77,122 @@ __device__ __forceinline__ int remap_tile(int bid, int ntile_pml, int ntile) {
     return base + x * q + (x < r ? x : r) + i;
 }
 
+// Copies nseg row segments of `seg_bytes` (16 elements of one row) into LDS
+// with direct 16-byte global->LDS loads, 1 KiB per wavefront instruction.
+// Segment k of the destination is segment k of the source list, whose global
+// address is base + k * stride_bytes.  Waves w, w+nw, ... take 1 KiB chunks.
+__device__ __forceinline__ void stage_rows(const char* __restrict__ base, size_t stride_bytes, int seg_bytes,
+                                           int nseg, char* lds, int wave, int nw, int lane) {
+    const int total = nseg * seg_bytes;
+    const int nchunk = (total + 1023) / 1024;
+    for (int c = wave; c < nchunk; c += nw) {
+        int byte = c * 1024 + lane * 16;
+        if (byte >= total) byte = total - 16;  // stays inside the source rows; lands in LDS padding
+        const int seg = byte / seg_bytes, off = byte - seg * seg_bytes;
+        __builtin_amdgcn_global_load_lds(base + seg * stride_bytes + off, lds + c * 1024, 16, 0, 0);
+    }
+}
+
+constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
+
 template <typename real, int N, int QT, bool KAPPA>
 __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p) {
     using M = Mma<real>;
     using v4 = typename M::v4;
-    constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, B = kBlock;
+    constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, B = kBlock, T = 16;
     constexpr int NF = 4 * Nfp;         // face nodes per element
     constexpr int PT = (Np + 15) / 16;  // node tiles
     constexpr int SP = (Np + 3) / 4;    // k-steps over nodes
     constexpr int SQM = 4 * QT;         // k-steps reserved over cubature points
     constexpr int SF = Nfp;             // k-steps over the face nodes
+    constexpr int QMAX = 16 * QT;       // cubature points the sigma staging can hold
     constexpr int OFF_VQ = 0;
     constexpr int OFF_PQ = OFF_VQ + QT * SP;
     constexpr int OFF_D = OFF_PQ + PT * SQM;
     constexpr int OFF_L = OFF_D + 3 * PT * SP;
     constexpr int NFRAG = OFF_L + PT * SF;
     constexpr int EHS = 6 * Np * B;
-    constexpr int FIT = (NF * 16 + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread
-    constexpr int NCHUNK = frag_chunks(NFRAG, sizeof(real));          // 1 KiB chunks of fragments
-    __shared__ __attribute__((aligned(16))) real fr[NCHUNK * 1024 / sizeof(real)];
-    __shared__ real fl[6 * NF * 16];  // flux [component][face node][element of the tile]
+    constexpr int FIT = (NF * T + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread
+    constexpr int RB = static_cast<int>(sizeof(real));
+    // LDS: operator fragments, the tile's E,H rows, sigma rows, geometry rows,
+    // neighbour offsets, and the flux (all padded to whole KiB for the staging copies)
+    constexpr int L_FR = pad1k(NFRAG * 64 * RB);
+    constexpr int L_EH = pad1k(6 * Np * T * RB);
+    constexpr int L_SG = pad1k(3 * QMAX * T * RB);
+    constexpr int L_GE = pad1k(kGeo * T * RB);
+    constexpr int L_NB = pad1k(NF * T * 4);
+    __shared__ __attribute__((aligned(16))) char smem[L_FR + L_EH + L_SG + L_GE + L_NB];
+    __shared__ real fl[6 * NF * T];  // flux [component][face node][element of the tile]
+    real* fr = reinterpret_cast<real*>(smem);
+    real* eh = reinterpret_cast<real*>(smem + L_FR);
+    real* sgs = reinterpret_cast<real*>(smem + L_FR + L_EH);
+    real* ges = reinterpret_cast<real*>(smem + L_FR + L_EH + L_SG);
+    int* nbs = reinterpret_cast<int*>(smem + L_FR + L_EH + L_SG + L_GE);
 
     const int tid = static_cast<int>(threadIdx.x);
     const int tile = __builtin_amdgcn_readfirstlane(remap_tile(blockIdx.x, 4 * p.nblk_pml, 4 * p.nblk));
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
-    const real* __restrict__ qin = static_cast<const real*>(p.q_in);
-    const real* __restrict__ geo0 = static_cast<const real*>(p.geo) + static_cast<size_t>(blk) * kGeo * B + 16 * sub;
-    const real* __restrict__ qt = qin + static_cast<size_t>(blk) * EHS + 16 * sub;
-
-    // wavefront u owns field component u of the tile
+    const int Nq = p.Nq;
     const int u = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int g = lane >> 4, j = lane & 15;
-    const int e = 16 * sub + j;
-    const int ax = (u < 3) ? u : u - 3;
-    const int bb = (ax == 2) ? 0 : ax + 1;
-    const int cc = (ax == 0) ? 2 : ax - 1;
-    const real* __restrict__ qe = qt + j;
-    const real* __restrict__ geo = geo0 + j;
-    const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
+    const int e = T * sub + j;
+    const real* __restrict__ qin = static_cast<const real*>(p.q_in);
 
-    // ---- operators to LDS by direct global->LDS loads (16 bytes per lane, 1 KiB per wavefront)
+    // ---- stage the tile into LDS (direct global->LDS loads)
     {
-        const char* __restrict__ src = static_cast<const char*>(p.frags);
-        char* dst = reinterpret_cast<char*>(fr);
-        for (int c = u; c < NCHUNK; c += 6)
-            __builtin_amdgcn_global_load_lds(src + c * 1024 + lane * 16, dst + c * 1024, 16, 0, 0);
+        const size_t row = static_cast<size_t>(B) * RB;  // bytes between rows of the blocked layout
+        stage_rows(reinterpret_cast<const char*>(p.frags), 1024, 1024, NFRAG * 64 * RB / 1024 + ((NFRAG * 64 * RB) % 1024 ? 1 : 0),
+                   smem, u, 6, lane);
+        stage_rows(reinterpret_cast<const char*>(qin + static_cast<size_t>(blk) * EHS + T * sub), row, T * RB, 6 * Np,
+                   smem + L_FR, u, 6, lane);
+        stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.geo) + static_cast<size_t>(blk) * kGeo * B + T * sub),
+                   row, T * RB, kGeo, smem + L_FR + L_EH + L_SG, u, 6, lane);
+        stage_rows(reinterpret_cast<const char*>(p.nbr + static_cast<size_t>(blk) * NF * B + T * sub), static_cast<size_t>(B) * 4,
+                   T * 4, NF, smem + L_FR + L_EH + L_SG + L_GE, u, 6, lane);
+        if (pml)
+            stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
+                       row, T * RB, 3 * Nq, smem + L_FR + L_EH, u, 6, lane);
     }
-    // ---- issue every load that does not depend on the flux before the barrier
-    real bf[SP], bp[SP], xb[SP], xc[SP];
-    const int fo = (u < 3) ? 3 : 0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // ---- per-wave loads that only this wave needs, issued to overlap the flux phase
+    const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
+    const size_t ebase = static_cast<size_t>(blk) * EHS + e;
+    real* __restrict__ rs = static_cast<real*>(p.res);
+    real* __restrict__ qo = static_cast<real*>(p.q_out);
+    const bool read_res = p.read_res != 0;
+    real bp[SP];
+    real rP[PT][4], qP[PT][4], rE[PT][4];
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
-        const bool ok = (SP * 4 == Np) || node < Np;
-        const int nd = ok ? node : 0;
-        bf[s] = pml ? qe[(u * Np + nd) * B] : real(0);
+        const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
         bp[s] = pml ? qin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-        xb[s] = qe[((fo + bb) * Np + nd) * B];
-        xc[s] = qe[((fo + cc) * Np + nd) * B];
-        if (!ok) bf[s] = bp[s] = xb[s] = xc[s] = real(0);
     }
-    const real sgn = (u < 3) ? real(1) : real(-1);
-    const real mrb = geo[bb * B], mrc = geo[cc * B];
-    const real msb = geo[(3 + bb) * B], msc = geo[(3 + cc) * B];
-    const real mtb = geo[(6 + bb) * B], mtc = geo[(6 + cc) * B];
+#pragma unroll
+    for (int t = 0; t < PT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int node = 16 * t + 4 * v + g;
+            const int nd = node < Np ? node : 0;
+            rP[t][v] = (pml && read_res) ? rs[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            qP[t][v] = pml ? qin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            rE[t][v] = read_res ? rs[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+        }
 
     // ---- upwind flux of all six components at the 4 Nfp face nodes, once per tile
     {
-        const int* __restrict__ nbr = p.nbr + static_cast<size_t>(blk) * NF * B + 16 * sub;
         const real alpha = static_cast<real>(p.alpha);
-        real own[FIT][6], nb[FIT][6], nv[FIT][4];
+        real nb[FIT][6];
         int vv[FIT];
 #pragma unroll
         for (int it = 0; it < FIT; ++it) {
             const int pi0 = tid + it * kMfmaThreads;
-            const int pi = pi0 < NF * 16 ? pi0 : 0;
-            const int fn = pi >> 4, jj = pi & 15;
-            const int fc = fn / Nfp;
-            const int jn = p.fmask[fn];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) own[it][c] = qt[(c * Np + jn) * B + jj];
-            vv[it] = nbr[fn * B + jj];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) nv[it][c] = geo0[(9 + 4 * fc + c) * B + jj];
-        }
-#pragma unroll
-        for (int it = 0; it < FIT; ++it) {
+            const int pi = pi0 < NF * T ? pi0 : 0;
+            vv[it] = nbs[pi];  // [face node][element]
             const int off = vv[it] >= 0 ? vv[it] : ~vv[it];
             const real* __restrict__ qp = qin + off;
 #pragma unroll
@@ -173,33 +201,39 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
 #pragma unroll
         for (int it = 0; it < FIT; ++it) {
             const int pi = tid + it * kMfmaThreads;
-            if (pi >= NF * 16) continue;
+            if (pi >= NF * T) continue;
+            const int fn = pi >> 4, jj = pi & 15;
+            const int fc = fn / Nfp;
+            const int jn = p.fmask[fn];
             const real sE = vv[it] >= 0 ? real(1) : real(-1);  // PEC wall: E+ = -E-, H+ = H-
-            const real dEx = own[it][0] - sE * nb[it][0], dEy = own[it][1] - sE * nb[it][1], dEz = own[it][2] - sE * nb[it][2];
-            const real dHx = own[it][3] - nb[it][3], dHy = own[it][4] - nb[it][4], dHz = own[it][5] - nb[it][5];
-            const real nx = nv[it][0], ny = nv[it][1], nz = nv[it][2];
-            const real hs = real(0.5) * nv[it][3];
+            const real dEx = eh[(0 * Np + jn) * T + jj] - sE * nb[it][0];
+            const real dEy = eh[(1 * Np + jn) * T + jj] - sE * nb[it][1];
+            const real dEz = eh[(2 * Np + jn) * T + jj] - sE * nb[it][2];
+            const real dHx = eh[(3 * Np + jn) * T + jj] - nb[it][3];
+            const real dHy = eh[(4 * Np + jn) * T + jj] - nb[it][4];
+            const real dHz = eh[(5 * Np + jn) * T + jj] - nb[it][5];
+            const real nx = ges[(9 + 4 * fc) * T + jj], ny = ges[(10 + 4 * fc) * T + jj], nz = ges[(11 + 4 * fc) * T + jj];
+            const real hs = real(0.5) * ges[(12 + 4 * fc) * T + jj];
             const real ndE = nx * dEx + ny * dEy + nz * dEz;
             const real ndH = nx * dHx + ny * dHy + nz * dHz;
-            real* f = fl + pi;  // (fn * 16 + jj)
-            f[0 * NF * 16] = hs * (-(ny * dHz - nz * dHy) + alpha * (nx * ndE - dEx));
-            f[1 * NF * 16] = hs * (-(nz * dHx - nx * dHz) + alpha * (ny * ndE - dEy));
-            f[2 * NF * 16] = hs * (-(nx * dHy - ny * dHx) + alpha * (nz * ndE - dEz));
-            f[3 * NF * 16] = hs * ((ny * dEz - nz * dEy) + alpha * (nx * ndH - dHx));
-            f[4 * NF * 16] = hs * ((nz * dEx - nx * dEz) + alpha * (ny * ndH - dHy));
-            f[5 * NF * 16] = hs * ((nx * dEy - ny * dEx) + alpha * (nz * ndH - dHz));
+            real* f = fl + pi;
+            f[0 * NF * T] = hs * (-(ny * dHz - nz * dHy) + alpha * (nx * ndE - dEx));
+            f[1 * NF * T] = hs * (-(nz * dHx - nx * dHz) + alpha * (ny * ndE - dEy));
+            f[2 * NF * T] = hs * (-(nx * dHy - ny * dHx) + alpha * (nz * ndE - dEz));
+            f[3 * NF * T] = hs * ((ny * dEz - nz * dEy) + alpha * (nx * ndH - dHx));
+            f[4 * NF * T] = hs * ((nz * dEx - nx * dEz) + alpha * (ny * ndH - dHy));
+            f[5 * NF * T] = hs * ((nx * dEy - ny * dEx) + alpha * (nz * ndH - dHz));
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // the direct loads into LDS have landed
     __syncthreads();
 
-    const int Nq = p.Nq;
     const int SQ = (Nq + 3) / 4;
-    real* __restrict__ rs = static_cast<real*>(p.res);
-    real* __restrict__ qo = static_cast<real*>(p.q_out);
+    const int ax = (u < 3) ? u : u - 3;
+    const int bb = (ax == 2) ? 0 : ax + 1;
+    const int cc = (ax == 0) ? 2 : ax - 1;
     const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b), dt = static_cast<real>(p.dt);
-    const bool read_res = p.read_res != 0;
     auto frag = [&](int f) -> real { return fr[f * 64 + lane]; };
+    auto ehv = [&](int c, int node) -> real { return eh[(c * Np + node) * T + j]; };
 
     v4 R[PT];
 #pragma unroll
@@ -208,78 +242,54 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     // ---- B. lift of the flux of component u (eqs. (15), (17))
 #pragma unroll
     for (int s = 0; s < SF; ++s) {
-        const real b = fl[(u * NF + 4 * s + g) * 16 + j];
+        const real b = fl[(u * NF + 4 * s + g) * T + j];
 #pragma unroll
         for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L + t * SF + s), b, R[t]);
     }
 
     // ---- C. volume curl: +curl H (E components), -curl E (H components)
-#pragma unroll
-    for (int s = 0; s < SP; ++s) {
-        const real gr = sgn * (mrb * xc[s] - mrc * xb[s]);
-        const real gs = sgn * (msb * xc[s] - msc * xb[s]);
-        const real gt = sgn * (mtb * xc[s] - mtc * xb[s]);
-#pragma unroll
-        for (int t = 0; t < PT; ++t) {
-            R[t] = M::run(frag(OFF_D + (0 * PT + t) * SP + s), gr, R[t]);
-            R[t] = M::run(frag(OFF_D + (1 * PT + t) * SP + s), gs, R[t]);
-            R[t] = M::run(frag(OFF_D + (2 * PT + t) * SP + s), gt, R[t]);
-        }
-    }
-
-    // residual and field of component u for the final update, issued before the products
-    real rold[PT][4], qold[PT][4];
     {
-        const size_t eb = static_cast<size_t>(blk) * EHS + e;
+        const int fo = (u < 3) ? 3 : 0;
+        const real sgn = (u < 3) ? real(1) : real(-1);
+        const real rb = sgn * ges[bb * T + j], rc = sgn * ges[cc * T + j];
+        const real sb = sgn * ges[(3 + bb) * T + j], sc = sgn * ges[(3 + cc) * T + j];
+        const real tb = sgn * ges[(6 + bb) * T + j], tc = sgn * ges[(6 + cc) * T + j];
 #pragma unroll
-        for (int t = 0; t < PT; ++t)
+        for (int s = 0; s < SP; ++s) {
+            const int node = 4 * s + g;
+            const bool ok = (SP * 4 == Np) || node < Np;
+            const real xb = ok ? ehv(fo + bb, node) : real(0);
+            const real xc = ok ? ehv(fo + cc, node) : real(0);
+            const real gr = rb * xc - rc * xb, gs = sb * xc - sc * xb, gt = tb * xc - tc * xb;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int node = 16 * t + 4 * v + g;
-                const size_t idx = eb + static_cast<size_t>(u * Np + (node < Np ? node : 0)) * B;
-                rold[t][v] = read_res ? rs[idx] : real(0);
-                qold[t][v] = qin[idx];
+            for (int t = 0; t < PT; ++t) {
+                R[t] = M::run(frag(OFF_D + (0 * PT + t) * SP + s), gr, R[t]);
+                R[t] = M::run(frag(OFF_D + (1 * PT + t) * SP + s), gs, R[t]);
+                R[t] = M::run(frag(OFF_D + (2 * PT + t) * SP + s), gt, R[t]);
             }
+        }
     }
 
     // ---- A. PML terms at the cubature points (eqs. (26)-(29))
     if (pml) {
-        const real* __restrict__ sg = static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + e;
         const real* __restrict__ kp =
             KAPPA ? static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + e : nullptr;
-        // coefficient samples and the residual / field of the auxiliary component, issued early
-        real sa[QT][4], sb[QT][4], sc[QT][4];
-#pragma unroll
-        for (int t = 0; t < QT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int q = 16 * t + 4 * v + g;
-                const int qq = q < Nq ? q : 0;
-                sa[t][v] = sg[(ax * Nq + qq) * B];
-                sb[t][v] = sg[(bb * Nq + qq) * B];
-                sc[t][v] = sg[(cc * Nq + qq) * B];
-            }
-        real rold[PT][4], qold[PT][4];
-#pragma unroll
-        for (int t = 0; t < PT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int node = 16 * t + 4 * v + g;
-                const size_t idx = pbase + static_cast<size_t>(u * Np + (node < Np ? node : 0)) * B;
-                rold[t][v] = read_res ? rs[idx] : real(0);
-                qold[t][v] = qin[idx];
-            }
         v4 VF[QT], VP[QT];
 #pragma unroll
         for (int t = 0; t < QT; ++t) VF[t] = VP[t] = v4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SP; ++s)
+        for (int s = 0; s < SP; ++s) {
+            const int node = 4 * s + g;
+            const bool ok = (SP * 4 == Np) || node < Np;
+            const real bf = ok ? ehv(u, node) : real(0);
+            const real bpv = ok ? bp[s] : real(0);
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
                 const real a = frag(OFF_VQ + t * SP + s);
-                VF[t] = M::run(a, bf[s], VF[t]);
-                VP[t] = M::run(a, bp[s], VP[t]);
+                VF[t] = M::run(a, bf, VF[t]);
+                VP[t] = M::run(a, bpv, VP[t]);
             }
+        }
         // eq. (9) at cubature point q = 16 t + 4 v + g: VF <- -t1, VP <- t2
 #pragma unroll
         for (int t = 0; t < QT; ++t)
@@ -288,19 +298,20 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 const int q = 16 * t + 4 * v + g;
                 real t1 = real(0), t2 = real(0);
                 if (q < Nq) {
+                    const real sa = sgs[(ax * Nq + q) * T + j], sbq = sgs[(bb * Nq + q) * T + j], scq = sgs[(cc * Nq + q) * T + j];
                     real bq, cq, dq, kinv;
                     if (KAPPA) {
                         const real ka = kp[(ax * Nq + q) * B], kb = kp[(bb * Nq + q) * B], kc = kp[(cc * Nq + q) * B];
                         kinv = real(1) / ka;
                         const real aa = kb * kc * kinv;
-                        bq = (sb[t][v] * kc + sc[t][v] * kb - aa * sa[t][v]) * kinv;
-                        cq = sb[t][v] * sc[t][v] - bq * sa[t][v];
-                        dq = sa[t][v] * kinv;
+                        bq = (sbq * kc + scq * kb - aa * sa) * kinv;
+                        cq = sbq * scq - bq * sa;
+                        dq = sa * kinv;
                     } else {
                         kinv = real(1);
-                        bq = sb[t][v] + sc[t][v] - sa[t][v];
-                        cq = sb[t][v] * sc[t][v] - bq * sa[t][v];
-                        dq = sa[t][v];
+                        bq = sbq + scq - sa;
+                        cq = sbq * scq - bq * sa;
+                        dq = sa;
                     }
                     const real vf = VF[t][v], vp = VP[t][v];
                     t1 = bq * vf + cq * vp;
@@ -309,7 +320,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 VF[t][v] = -t1;
                 VP[t][v] = t2;
             }
-        // rhs_P = P_q t2 and R = -P_q t1
+        // rhs_P = P_q t2 and R -= P_q t1
         v4 RP[PT];
 #pragma unroll
         for (int t = 0; t < PT; ++t) RP[t] = v4{0, 0, 0, 0};
@@ -335,9 +346,9 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 const int node = 16 * t + 4 * v + g;
                 if (node < Np) {
                     const size_t idx = pbase + static_cast<size_t>(u * Np + node) * B;
-                    const real r = dt * RP[t][v] + rkA * rold[t][v];
+                    const real r = dt * RP[t][v] + rkA * rP[t][v];
                     rs[idx] = r;
-                    qo[idx] = qold[t][v] + rkB * r;
+                    qo[idx] = qP[t][v] + rkB * r;
                 }
             }
     }
@@ -404,21 +415,18 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     }
 
     // ---- LSERK4 update of component u
-    {
-        const size_t eb = static_cast<size_t>(blk) * EHS + e;
 #pragma unroll
-        for (int t = 0; t < PT; ++t)
+    for (int t = 0; t < PT; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int node = 16 * t + 4 * v + g;
-                if (node < Np) {
-                    const size_t idx = eb + static_cast<size_t>(u * Np + node) * B;
-                    const real r = dt * R[t][v] + rkA * rold[t][v];
-                    rs[idx] = r;
-                    qo[idx] = qold[t][v] + rkB * r;
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int node = 16 * t + 4 * v + g;
+            if (node < Np) {
+                const size_t idx = ebase + static_cast<size_t>(u * Np + node) * B;
+                const real r = dt * R[t][v] + rkA * rE[t][v];
+                rs[idx] = r;
+                qo[idx] = ehv(u, node) + rkB * r;
             }
-    }
+        }
 }
 
 template <typename real, int N, int QT, bool K>
@@ -432,6 +440,8 @@ int launch_k(bool k, const StageParams& p, hipStream_t s) {
     return k ? launch_t<real, N, QT, true>(p, s) : launch_t<real, N, QT, false>(p, s);
 }
 
+// Order / cubature-tile combinations with a matrix-core kernel.  FP64 at
+// N = 4 would need more than the 160 KiB of LDS of a compute unit.
 template <typename real>
 int launch_r(int N, int QT, bool k, const StageParams& p, hipStream_t s) {
     switch (N * 10 + QT) {
@@ -441,25 +451,34 @@ int launch_r(int N, int QT, bool k, const StageParams& p, hipStream_t s) {
         case 22: return launch_k<real, 2, 2>(k, p, s);
         case 32: return launch_k<real, 3, 2>(k, p, s);
         case 33: return launch_k<real, 3, 3>(k, p, s);
-        case 43: return launch_k<real, 4, 3>(k, p, s);
-        case 44: return launch_k<real, 4, 4>(k, p, s);
+        default: return -1;
+    }
+}
+
+int launch_r4(int QT, bool k, const StageParams& p, hipStream_t s) {
+    switch (QT) {
+        case 3: return launch_k<float, 4, 3>(k, p, s);
+        case 4: return launch_k<float, 4, 4>(k, p, s);
         default: return -1;
     }
 }
 
 }  // namespace
 
-bool mfma_supported(int N, int Nq) {
+bool mfma_supported(int N, int Nq, int precision) {
     const int QT = (Nq + 15) / 16;
     switch (N * 10 + QT) {
-        case 11: case 12: case 21: case 22: case 32: case 33: case 43: case 44: return true;
+        case 11: case 12: case 21: case 22: case 32: case 33: return true;
+        case 43: case 44: return precision != 0;
         default: return false;
     }
 }
 
 int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s) {
     const int QT = (p.Nq + 15) / 16;
-    return precision == 0 ? launch_r<double>(N, QT, has_kappa, p, s) : launch_r<float>(N, QT, has_kappa, p, s);
+    if (precision == 0) return launch_r<double>(N, QT, has_kappa, p, s);
+    if (N == 4) return launch_r4(QT, has_kappa, p, s);
+    return launch_r<float>(N, QT, has_kappa, p, s);
 }
 
 }  // namespace wdg

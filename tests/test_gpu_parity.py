@@ -72,7 +72,7 @@ def test_rhs_parity_fp64(wdg, name, over, kernel):
     cfg = inputs.config(name, **over)
     _say(f"rhs parity {name} {over} kernel {kernel}")
     sim, osim = _pair(wdg, cfg, init="random", seed=3, kernel=kernel)
-    if kernel == 0:
+    if kernel == 0 and cfg["N"] <= 3:  # FP64 at N = 4 runs the scalar-operand kernel
         assert sim.dims.kernel == wdg.WDG_KERNEL_MFMA
     t = 0.61
     sim.rhs(t)
