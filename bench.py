@@ -12,7 +12,7 @@ inverse mass and the Runge-Kutta update) plus the probe readout.  Fields live
 in HBM before the timed region starts.  The metric is
 K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
 
-Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--copy-calibration MIB]
 """
 from __future__ import annotations
 
@@ -26,6 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+# HBM bytes per stage launch from rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00
+# (scale factors from a 1 GiB device copy), taken on the kernel source with
+# this sha256; reported only while the source is unchanged.
+MEASURED_TRAFFIC = {
+    "source_sha256": "0ffa1410f5e53991d4ee5adf5c0e071d75be0671101c7be8246dcb74da1d8a8a",
+    "stage_mfma_kernel<double,N=3,Nq=24>": (119995.8 * 2.0 + 160560.0) * 1024,
+    "stage_mfma_kernel<float,N=3,Nq=24>": (64164.7 * 2.0 + 97069.9) * 1024,
+}
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)
 
@@ -54,6 +62,15 @@ def algorithmic_traffic(d, word: int):
     fl_common = 36 * Np * Np + 48 * Nfp * Np + 160 * Nfp
     flops_per_launch = Kp * (fl_common + 72 * Nq * Np) + Ki * fl_common
     return bytes_per_launch, flops_per_launch
+
+
+def measured_traffic(kernel):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2006_02551_amd", "csrc", "kernels_mfma.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != MEASURED_TRAFFIC["source_sha256"]:
+            return None
+    return MEASURED_TRAFFIC.get(kernel)
 
 
 def run_gpu(cfg, precision, steps, warmup):
@@ -130,6 +147,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB three times (a known-size reference for "
+                         "hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the element-partitioned "
@@ -141,6 +161,15 @@ def main():
     from paper_2006_02551_amd import inputs, wdg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copied {args.copy_calibration} MiB three times", file=sys.stderr, flush=True)
+        del src, dst
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
     r64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup)
@@ -173,10 +202,11 @@ def main():
                  "speedup_vs_fp64": r32["value"] / r64["value"],
                  "roofline": {"bound": "hbm", "achieved": r32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": r32["achieved_gbs"] / HBM_PEAK_GBS,
+                              "traffic": measured_traffic(r32["kernel"]),
                               "achieved_tflops": r32["achieved_tflops"],
                               "flop_frac": r32["achieved_tflops"] / FP32_PEAK_TFLOPS}},
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(r64["kernel"]),
                      "kernel": r64["kernel"], "stage_launch_us": r64["stage_launch_us"],
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "achieved_tflops": r64["achieved_tflops"],

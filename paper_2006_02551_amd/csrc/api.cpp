@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -226,33 +227,44 @@ void upload_setup(wdg_ctx* c) {
     c->off_PqT = push(transpose(R.Pq, Np, Nq));
     c->ops.upload(to_real(ops, c->precision).data(), ops.size() * c->rsize);
 
-    // MFMA A-operand fragments.  Lane l of fragment (tile p, k-step s) holds
-    // Op[n(16p + l%16)][4s + l/16]; n() is the row permutation that makes MFMA
-    // register v of lane group g hold quantity 16p + 4v + g (the FP64 MFMA
-    // returns row g + 4v in register v, the FP32 MFMA row 4g + v).
+    // MFMA A-operand fragments (layout in device.hpp): V_q with full tiles (its
+    // row count N_q is a run-time value in the kernel), then P_q, D_r, D_s, D_t
+    // and LIFT, whose last tile of N_p rows is stored compact.
     c->mfma_ok = mfma_supported(R.N, Nq, c->precision);
     if (c->mfma_ok) {
         const int PT = (Np + 15) / 16, SP = (Np + 3) / 4, QT = (Nq + 15) / 16, SQM = 4 * QT, SF = Nfp;
         const bool f64 = c->precision == WDG_FP64;
-        auto quantity = [&](int r) { const int rr = r % 16; return 16 * (r / 16) + (f64 ? rr : 4 * (rr % 4) + rr / 4); };
+        auto qloc = [&](int rr) { return f64 ? rr : 4 * (rr % 4) + rr / 4; };
         std::vector<double> fr;
-        auto add = [&](const Mat& X, int rows, int cols, int tiles, int ksteps) {
+        auto add = [&](const Mat& X, int rows, int cols, int tiles, int ksteps, bool compact) {
+            const size_t start = fr.size();
             for (int t = 0; t < tiles; ++t)
-                for (int ks = 0; ks < ksteps; ++ks)
-                    for (int l = 0; l < 64; ++l) {
-                        const int row = quantity(16 * t + l % 16), col = 4 * ks + l / 16;
-                        fr.push_back(row < rows && col < cols ? X[static_cast<size_t>(row) * cols + col] : 0.0);
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    if (compact && t == tiles - 1) {
+                        const int m = rows - 16 * t;
+                        for (int k = 0; k < 4; ++k)
+                            for (int i = 0; i < m; ++i) {
+                                const int col = 4 * ks + k;
+                                fr.push_back(col < cols ? X[static_cast<size_t>(16 * t + i) * cols + col] : 0.0);
+                            }
+                    } else {
+                        for (int l = 0; l < 64; ++l) {
+                            const int row = 16 * t + qloc(l % 16), col = 4 * ks + l / 16;
+                            fr.push_back(row < rows && col < cols ? X[static_cast<size_t>(row) * cols + col] : 0.0);
+                        }
                     }
+                }
+            if (fr.size() - start != static_cast<size_t>(frag_words(rows, tiles, ksteps, compact)))
+                throw std::logic_error("fragment size");
         };
-        add(R.Vq, Nq, Np, QT, SP);
-        add(R.Pq, Np, Nq, PT, SQM);
-        add(R.Dr, Np, Np, PT, SP);
-        add(R.Ds, Np, Np, PT, SP);
-        add(R.Dt, Np, Np, PT, SP);
-        add(R.LIFT, Np, 4 * Nfp, PT, SF);
+        add(R.Vq, Nq, Np, QT, SP, false);
+        add(R.Pq, Np, Nq, PT, SQM, true);
+        add(R.Dr, Np, Np, PT, SP, true);
+        add(R.Ds, Np, Np, PT, SP, true);
+        add(R.Dt, Np, Np, PT, SP, true);
+        add(R.LIFT, Np, 4 * Nfp, PT, SF, true);
         // padded to whole 1 KiB chunks (the kernel copies it with 16-byte direct loads into LDS)
-        const int nfrag = static_cast<int>(fr.size() / 64);
-        fr.resize(static_cast<size_t>(frag_chunks(nfrag, static_cast<int>(c->rsize))) * 1024 / c->rsize, 0.0);
+        fr.resize(static_cast<size_t>(frag_chunks(static_cast<int>(fr.size()), static_cast<int>(c->rsize))) * 1024 / c->rsize, 0.0);
         c->frags.upload(to_real(fr, c->precision).data(), fr.size() * c->rsize);
         c->kernel = WDG_KERNEL_MFMA;
     }

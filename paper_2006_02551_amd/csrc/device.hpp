@@ -23,9 +23,23 @@ constexpr int kBlock = 64;   // element slots per block (one wavefront)
 constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
 constexpr int kMfmaThreads = 6 * 64;  // MFMA kernel: one wavefront per component of a 16-element tile
+constexpr int kMfmaTiles = 2;          // MFMA kernel: 16-element tiles per workgroup (1, 2 or 4)
 
-// Number of 1 KiB chunks that hold nfrag MFMA operand fragments of 64 words.
-constexpr int frag_chunks(int nfrag, int word_bytes) { return (nfrag * 64 * word_bytes + 1023) / 1024; }
+// MFMA operand fragments.  An operator with `rows` rows is cut into tiles of
+// 16 rows; for every tile t and k-step s (4 columns) there is one fragment.
+// A full tile's fragment is 64 words, lane l holding
+//   Op[16 t + qloc(l % 16)][4 s + l / 16],
+// where qloc(r) = r for the FP64 MFMA and 4 (r % 4) + r / 4 for the FP32 MFMA
+// (so that register v of lane group g of a product holds row 16 t + 4 v + g).
+// When an operator is stored compact, its last tile keeps only its m valid
+// rows: 4 m words Op[16 t + i][4 s + k] at k m + i, and lane l reads word
+// (l / 16) m + min(qloc(l % 16), m - 1) (rows past m repeat a valid row; the
+// kernels never use those output rows).
+constexpr int frag_words(int rows, int tiles, int ksteps, bool compact) {
+    return compact ? ((tiles - 1) * 64 + 4 * (rows - 16 * (tiles - 1))) * ksteps : tiles * 64 * ksteps;
+}
+// Number of 1 KiB chunks that hold nwords fragment words.
+constexpr int frag_chunks(int nwords, int word_bytes) { return (nwords * word_bytes + 1023) / 1024; }
 
 struct StageParams {
     const void* q_in;

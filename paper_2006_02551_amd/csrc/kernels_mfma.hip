@@ -7,13 +7,16 @@
 //
 //   Out (M x 16 elements) = Op (M x K) * X (K x 16 elements)
 //
-// A workgroup owns a tile of 16 elements (the columns) and has six
-// wavefronts, one per field component u.  The reference operators are the A
-// operands; they are stored on the host in fragment order (tile p, k-step s,
-// lane), copied once per workgroup into LDS and read with one 64-lane LDS load
-// per fragment.  Field data are the B operands.  The upwind flux of all six
-// components is computed once per tile by the whole workgroup (one face node
-// and element per thread) and shared through LDS.
+// A tile is 16 elements (the columns), handled by six wavefronts, one per
+// field component u; a workgroup takes kMfmaTiles adjacent tiles so that its
+// wavefront count is a multiple of the four SIMDs of a compute unit.  The
+// reference operators are the A operands; they are stored on the host in
+// fragment order (operator tile, k-step, lane; the last tile of an N_p-row
+// operator compact, see device.hpp), copied once per workgroup into LDS and
+// read with one 64-lane LDS load per fragment.  Field data are the B
+// operands.  The upwind flux of all six components is computed once per tile
+// by its 384 threads (one face node and element per thread) and shared
+// through LDS, in two rounds of half the face nodes each.
 //
 // Register chaining.  Lane l = 16 g + j holds column j; an MFMA result keeps
 // four values per lane (register v).  The host permutes the rows of every
@@ -28,6 +31,7 @@
 //
 // Per PML tile, wavefront u (f = E or H, P its auxiliary field):
 //   B. R = LIFT (Fscale * upwind flux), flux read from LDS in B layout
+//      (after each of the two flux rounds)
 //   C. R += D_r G_r + D_s G_s + D_t G_t, G_d = metric-weighted components
 //   A. VF = V_q f_u, VP = V_q P_u; t1 = b VF + c VP, t2 = kappa^-1 VF - d VP
 //      (eq. (9) at the cubature points); rhs_P = P_q t2 (then its LSERK
@@ -95,42 +99,78 @@ __device__ __forceinline__ void stage_rows(const char* __restrict__ base, size_t
 
 constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
 
+// Compile-time shape of the kernel for one precision, order and number of
+// cubature tiles.
+template <typename real, int N, int QT>
+struct Shape {
+    static constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, T = 16;
+    static constexpr int NF = 4 * Nfp;             // face nodes per element
+    static constexpr int PT = (Np + 15) / 16;      // node tiles
+    static constexpr int MR = Np - 16 * (PT - 1);  // rows of the last node tile
+    static constexpr int SP = (Np + 3) / 4;        // k-steps over nodes
+    static constexpr int SQM = 4 * QT;             // k-steps reserved over cubature points
+    static constexpr int SF = Nfp;                 // k-steps over the face nodes
+    static constexpr int S0 = (SF + 1) / 2;        // k-steps (4 face nodes each) of the first flux round
+    static constexpr int QMAX = 16 * QT;           // cubature points the sigma staging can hold
+    static constexpr int RB = static_cast<int>(sizeof(real));
+    // fragment words of each operator (V_q full tiles; P_q, D_r,s,t, LIFT compact last tile)
+    static constexpr int W_VQ = frag_words(QMAX, QT, SP, false);
+    static constexpr int W_PQ = frag_words(Np, PT, SQM, true);
+    static constexpr int W_D = frag_words(Np, PT, SP, true);
+    static constexpr int W_L = frag_words(Np, PT, SF, true);
+    static constexpr int OFF_VQ = 0, OFF_PQ = W_VQ, OFF_D = OFF_PQ + W_PQ, OFF_L = OFF_D + 3 * W_D;
+    static constexpr int NW = OFF_L + W_L;
+    static constexpr int NFH = 4 * S0;  // face nodes per flux round (the second round has NF - NFH)
+    // LDS: operator fragments (shared by the workgroup), then per tile its E,H
+    // rows, sigma rows, geometry rows and neighbour offsets (all padded to whole
+    // KiB for the staging copies), and per tile the flux of one round
+    static constexpr int L_FR = pad1k(NW * RB);
+    static constexpr int L_EH = pad1k(6 * Np * T * RB);
+    static constexpr int L_SG = pad1k(3 * QMAX * T * RB);
+    static constexpr int L_GE = pad1k(kGeo * T * RB);
+    static constexpr int L_NB = pad1k(NF * T * 4);
+    static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
+    static constexpr int L_FL = 6 * NFH * T * RB;
+    static constexpr int LDS = L_FR + kMfmaTiles * (L_TL + L_FL);
+    // Two workgroups per compute unit (6 wavefronts per SIMD) where their LDS
+    // fits in the 160 KiB of a compute unit; the compiler then keeps the
+    // registers to that occupancy.
+    static constexpr int WAVES_PER_SIMD = 2 * LDS <= 160 * 1024 ? 6 : 1;
+};
+
 template <typename real, int N, int QT, bool KAPPA>
-__global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p) {
+__global__ __launch_bounds__(kMfmaTiles * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT>::WAVES_PER_SIMD)))
+void stage_mfma_kernel(StageParams p) {
     using M = Mma<real>;
     using v4 = typename M::v4;
-    constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, B = kBlock, T = 16;
-    constexpr int NF = 4 * Nfp;         // face nodes per element
-    constexpr int PT = (Np + 15) / 16;  // node tiles
-    constexpr int SP = (Np + 3) / 4;    // k-steps over nodes
-    constexpr int SQM = 4 * QT;         // k-steps reserved over cubature points
-    constexpr int SF = Nfp;             // k-steps over the face nodes
-    constexpr int QMAX = 16 * QT;       // cubature points the sigma staging can hold
-    constexpr int OFF_VQ = 0;
-    constexpr int OFF_PQ = OFF_VQ + QT * SP;
-    constexpr int OFF_D = OFF_PQ + PT * SQM;
-    constexpr int OFF_L = OFF_D + 3 * PT * SP;
-    constexpr int NFRAG = OFF_L + PT * SF;
+    using S = Shape<real, N, QT>;
+    constexpr int Np = S::Np, Nfp = S::Nfp, B = kBlock, T = S::T;
+    constexpr int NF = S::NF, PT = S::PT, MR = S::MR, SP = S::SP, SQM = S::SQM, SF = S::SF, S0 = S::S0;
+    constexpr bool F64 = sizeof(real) == 8;
+    constexpr int W_D = S::W_D, OFF_VQ = S::OFF_VQ, OFF_PQ = S::OFF_PQ, OFF_D = S::OFF_D, OFF_L = S::OFF_L;
     constexpr int EHS = 6 * Np * B;
-    constexpr int FIT = (NF * T + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread
-    constexpr int RB = static_cast<int>(sizeof(real));
-    // LDS: operator fragments, the tile's E,H rows, sigma rows, geometry rows,
-    // neighbour offsets, and the flux (all padded to whole KiB for the staging copies)
-    constexpr int L_FR = pad1k(NFRAG * 64 * RB);
-    constexpr int L_EH = pad1k(6 * Np * T * RB);
-    constexpr int L_SG = pad1k(3 * QMAX * T * RB);
-    constexpr int L_GE = pad1k(kGeo * T * RB);
-    constexpr int L_NB = pad1k(NF * T * 4);
-    __shared__ __attribute__((aligned(16))) char smem[L_FR + L_EH + L_SG + L_GE + L_NB];
-    __shared__ real fl[6 * NF * T];  // flux [component][face node][element of the tile]
-    real* fr = reinterpret_cast<real*>(smem);
-    real* eh = reinterpret_cast<real*>(smem + L_FR);
-    real* sgs = reinterpret_cast<real*>(smem + L_FR + L_EH);
-    real* ges = reinterpret_cast<real*>(smem + L_FR + L_EH + L_SG);
-    int* nbs = reinterpret_cast<int*>(smem + L_FR + L_EH + L_SG + L_GE);
+    constexpr int NFH = S::NFH;
+    constexpr int FIT = (NFH * T + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread and round
+    constexpr int RB = S::RB;
+    constexpr int L_FR = S::L_FR, L_EH = S::L_EH, L_SG = S::L_SG, L_GE = S::L_GE, L_TL = S::L_TL;
+    __shared__ __attribute__((aligned(16))) char smem[L_FR + kMfmaTiles * L_TL];
+    __shared__ real fls[kMfmaTiles][6 * NFH * T];  // flux [component][face node of the round][element of the tile]
 
-    const int tid = static_cast<int>(threadIdx.x);
-    const int tile = __builtin_amdgcn_readfirstlane(remap_tile(blockIdx.x, 4 * p.nblk_pml, 4 * p.nblk));
+    // Workgroup: kMfmaTiles adjacent tiles of one element block, six
+    // wavefronts each (a multiple of four wavefronts keeps the four SIMDs of a
+    // compute unit equally loaded); the operator fragments are shared.
+    const int h = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kMfmaThreads);
+    const int tid = static_cast<int>(threadIdx.x) - h * kMfmaThreads;
+    real* fr = reinterpret_cast<real*>(smem);
+    char* tl = smem + L_FR + h * L_TL;
+    real* eh = reinterpret_cast<real*>(tl);
+    real* sgs = reinterpret_cast<real*>(tl + L_EH);
+    real* ges = reinterpret_cast<real*>(tl + L_EH + L_SG);
+    int* nbs = reinterpret_cast<int*>(tl + L_EH + L_SG + L_GE);
+    real* fl = fls[h];
+
+    const int tile = __builtin_amdgcn_readfirstlane(
+        kMfmaTiles * remap_tile(blockIdx.x, 4 / kMfmaTiles * p.nblk_pml, 4 / kMfmaTiles * p.nblk) + h);
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
     const int Nq = p.Nq;
@@ -143,20 +183,47 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
     // ---- stage the tile into LDS (direct global->LDS loads)
     {
         const size_t row = static_cast<size_t>(B) * RB;  // bytes between rows of the blocked layout
-        stage_rows(reinterpret_cast<const char*>(p.frags), 1024, 1024, NFRAG * 64 * RB / 1024 + ((NFRAG * 64 * RB) % 1024 ? 1 : 0),
-                   smem, u, 6, lane);
+        stage_rows(reinterpret_cast<const char*>(p.frags), 1024, 1024, L_FR / 1024, smem, h * 6 + u, 6 * kMfmaTiles, lane);
         stage_rows(reinterpret_cast<const char*>(qin + static_cast<size_t>(blk) * EHS + T * sub), row, T * RB, 6 * Np,
-                   smem + L_FR, u, 6, lane);
+                   tl, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.geo) + static_cast<size_t>(blk) * kGeo * B + T * sub),
-                   row, T * RB, kGeo, smem + L_FR + L_EH + L_SG, u, 6, lane);
+                   row, T * RB, kGeo, tl + L_EH + L_SG, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(p.nbr + static_cast<size_t>(blk) * NF * B + T * sub), static_cast<size_t>(B) * 4,
-                   T * 4, NF, smem + L_FR + L_EH + L_SG + L_GE, u, 6, lane);
+                   T * 4, NF, tl + L_EH + L_SG + L_GE, u, 6, lane);
         if (pml)
             stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
-                       row, T * RB, 3 * Nq, smem + L_FR + L_EH, u, 6, lane);
+                       row, T * RB, 3 * Nq, tl + L_EH, u, 6, lane);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+
+    // ---- neighbour traces for both flux rounds.  A neighbour inside this tile
+    // (and the own trace at a PEC wall) is read from the staged E,H rows at
+    // flux time (loc >= 0); the others are fetched from global memory now.
+    real nb[2][FIT][6];
+    int loc[2][FIT], vw[2][FIT];
+    {
+        const int base = blk * EHS + T * sub;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int it = 0; it < FIT; ++it) {
+                const int nitem = (r == 0 ? NFH : NF - NFH) * T;
+                const int pi0 = tid + it * kMfmaThreads;
+                const int pi = (pi0 < nitem ? pi0 : 0) + r * NFH * T;  // [face node][element]
+                const int vv = nbs[pi];
+                const int off = vv >= 0 ? vv : ~vv;
+                const int rel = off - base;
+                const bool in_tile = static_cast<unsigned>(rel) < static_cast<unsigned>(Np * B) && (rel & (B - 1)) < T;
+                vw[r][it] = vv;
+                loc[r][it] = in_tile ? (rel >> 6) * T + (rel & (B - 1)) : -1;
+                if (!in_tile) {
+                    const real* __restrict__ qp = qin + off;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) nb[r][it][c] = qp[c * Np * B];
+                }
+            }
+    }
 
     // ---- per-wave loads that only this wave needs, issued to overlap the flux phase
     const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
@@ -183,69 +250,73 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
             rE[t][v] = read_res ? rs[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0);
         }
 
-    // ---- upwind flux of all six components at the 4 Nfp face nodes, once per tile
-    {
-        const real alpha = static_cast<real>(p.alpha);
-        real nb[FIT][6];
-        int vv[FIT];
-#pragma unroll
-        for (int it = 0; it < FIT; ++it) {
-            const int pi0 = tid + it * kMfmaThreads;
-            const int pi = pi0 < NF * T ? pi0 : 0;
-            vv[it] = nbs[pi];  // [face node][element]
-            const int off = vv[it] >= 0 ? vv[it] : ~vv[it];
-            const real* __restrict__ qp = qin + off;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) nb[it][c] = qp[c * Np * B];
-        }
-#pragma unroll
-        for (int it = 0; it < FIT; ++it) {
-            const int pi = tid + it * kMfmaThreads;
-            if (pi >= NF * T) continue;
-            const int fn = pi >> 4, jj = pi & 15;
-            const int fc = fn / Nfp;
-            const int jn = p.fmask[fn];
-            const real sE = vv[it] >= 0 ? real(1) : real(-1);  // PEC wall: E+ = -E-, H+ = H-
-            const real dEx = eh[(0 * Np + jn) * T + jj] - sE * nb[it][0];
-            const real dEy = eh[(1 * Np + jn) * T + jj] - sE * nb[it][1];
-            const real dEz = eh[(2 * Np + jn) * T + jj] - sE * nb[it][2];
-            const real dHx = eh[(3 * Np + jn) * T + jj] - nb[it][3];
-            const real dHy = eh[(4 * Np + jn) * T + jj] - nb[it][4];
-            const real dHz = eh[(5 * Np + jn) * T + jj] - nb[it][5];
-            const real nx = ges[(9 + 4 * fc) * T + jj], ny = ges[(10 + 4 * fc) * T + jj], nz = ges[(11 + 4 * fc) * T + jj];
-            const real hs = real(0.5) * ges[(12 + 4 * fc) * T + jj];
-            const real ndE = nx * dEx + ny * dEy + nz * dEz;
-            const real ndH = nx * dHx + ny * dHy + nz * dHz;
-            real* f = fl + pi;
-            f[0 * NF * T] = hs * (-(ny * dHz - nz * dHy) + alpha * (nx * ndE - dEx));
-            f[1 * NF * T] = hs * (-(nz * dHx - nx * dHz) + alpha * (ny * ndE - dEy));
-            f[2 * NF * T] = hs * (-(nx * dHy - ny * dHx) + alpha * (nz * ndE - dEz));
-            f[3 * NF * T] = hs * ((ny * dEz - nz * dEy) + alpha * (nx * ndH - dHx));
-            f[4 * NF * T] = hs * ((nz * dEx - nx * dEz) + alpha * (ny * ndH - dHy));
-            f[5 * NF * T] = hs * ((nx * dEy - ny * dEx) + alpha * (nz * ndH - dHz));
-        }
-    }
-    __syncthreads();
-
-    const int SQ = (Nq + 3) / 4;
-    const int ax = (u < 3) ? u : u - 3;
-    const int bb = (ax == 2) ? 0 : ax + 1;
-    const int cc = (ax == 0) ? 2 : ax - 1;
-    const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b), dt = static_cast<real>(p.dt);
-    auto frag = [&](int f) -> real { return fr[f * 64 + lane]; };
+    // Fragment word of lane `lane` for operator tile t (of nt) and k-step s (of K k-steps).
+    const int lq = F64 ? (lane & 15) : 4 * (lane & 3) + ((lane & 15) >> 2);
+    const int lp = (lane >> 4) * MR + (lq < MR ? lq : MR - 1);  // lane's word in a compact tile
+    auto frag = [&](int off, int t, int s, int K) -> real {
+        return t < PT - 1 ? fr[off + (t * K + s) * 64 + lane] : fr[off + (PT - 1) * K * 64 + s * 4 * MR + lp];
+    };
+    auto fragq = [&](int t, int s) -> real { return fr[OFF_VQ + (t * SP + s) * 64 + lane]; };
     auto ehv = [&](int c, int node) -> real { return eh[(c * Np + node) * T + j]; };
 
     v4 R[PT];
 #pragma unroll
     for (int t = 0; t < PT; ++t) R[t] = v4{0, 0, 0, 0};
 
-    // ---- B. lift of the flux of component u (eqs. (15), (17))
+    // ---- upwind flux of all six components (once per tile, shared through
+    // LDS) and B. its lift for component u (eqs. (15)-(17)), in two rounds of
+    // face nodes so that the flux buffer holds half of them
+    {
+        const real alpha = static_cast<real>(p.alpha);
 #pragma unroll
-    for (int s = 0; s < SF; ++s) {
-        const real b = fl[(u * NF + 4 * s + g) * T + j];
+        for (int r = 0; r < 2; ++r) {
+            const int nitem = (r == 0 ? NFH : NF - NFH) * T;
+            if (r == 1) __syncthreads();  // the first round's lift has read fl
 #pragma unroll
-        for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L + t * SF + s), b, R[t]);
+            for (int it = 0; it < FIT; ++it) {
+                const int pi = tid + it * kMfmaThreads;
+                if (pi >= nitem) continue;
+                const int fn = r * NFH + (pi >> 4), jj = pi & 15;
+                const int fc = fn / Nfp;
+                const int jn = p.fmask[fn];
+                const int jo = jn * T + jj;
+                real nv[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) nv[c] = loc[r][it] >= 0 ? eh[c * Np * T + loc[r][it]] : nb[r][it][c];
+                const real sE = vw[r][it] >= 0 ? real(1) : real(-1);  // PEC wall: E+ = -E-, H+ = H-
+                const real dEx = eh[0 * Np * T + jo] - sE * nv[0];
+                const real dEy = eh[1 * Np * T + jo] - sE * nv[1];
+                const real dEz = eh[2 * Np * T + jo] - sE * nv[2];
+                const real dHx = eh[3 * Np * T + jo] - nv[3];
+                const real dHy = eh[4 * Np * T + jo] - nv[4];
+                const real dHz = eh[5 * Np * T + jo] - nv[5];
+                const real nx = ges[(9 + 4 * fc) * T + jj], ny = ges[(10 + 4 * fc) * T + jj], nz = ges[(11 + 4 * fc) * T + jj];
+                const real hs = real(0.5) * ges[(12 + 4 * fc) * T + jj];
+                const real ndE = nx * dEx + ny * dEy + nz * dEz;
+                const real ndH = nx * dHx + ny * dHy + nz * dHz;
+                real* f = fl + pi;
+                f[0 * NFH * T] = hs * (-(ny * dHz - nz * dHy) + alpha * (nx * ndE - dEx));
+                f[1 * NFH * T] = hs * (-(nz * dHx - nx * dHz) + alpha * (ny * ndE - dEy));
+                f[2 * NFH * T] = hs * (-(nx * dHy - ny * dHx) + alpha * (nz * ndE - dEz));
+                f[3 * NFH * T] = hs * ((ny * dEz - nz * dEy) + alpha * (nx * ndH - dHx));
+                f[4 * NFH * T] = hs * ((nz * dEx - nx * dEz) + alpha * (ny * ndH - dHy));
+                f[5 * NFH * T] = hs * ((nx * dEy - ny * dEx) + alpha * (nz * ndH - dHz));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = r * S0; s < (r == 0 ? S0 : SF); ++s) {
+                const real b = fl[(u * NFH + 4 * (s - r * S0) + g) * T + j];
+#pragma unroll
+                for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L, t, s, SF), b, R[t]);
+            }
+        }
     }
+
+    const int SQ = (Nq + 3) / 4;
+    const int ax = (u < 3) ? u : u - 3;
+    const int bb = (ax == 2) ? 0 : ax + 1;
+    const int cc = (ax == 0) ? 2 : ax - 1;
+    const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b), dt = static_cast<real>(p.dt);
 
     // ---- C. volume curl: +curl H (E components), -curl E (H components)
     {
@@ -263,9 +334,9 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
             const real gr = rb * xc - rc * xb, gs = sb * xc - sc * xb, gt = tb * xc - tc * xb;
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
-                R[t] = M::run(frag(OFF_D + (0 * PT + t) * SP + s), gr, R[t]);
-                R[t] = M::run(frag(OFF_D + (1 * PT + t) * SP + s), gs, R[t]);
-                R[t] = M::run(frag(OFF_D + (2 * PT + t) * SP + s), gt, R[t]);
+                R[t] = M::run(frag(OFF_D + 0 * W_D, t, s, SP), gr, R[t]);
+                R[t] = M::run(frag(OFF_D + 1 * W_D, t, s, SP), gs, R[t]);
+                R[t] = M::run(frag(OFF_D + 2 * W_D, t, s, SP), gt, R[t]);
             }
         }
     }
@@ -285,7 +356,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
             const real bpv = ok ? bp[s] : real(0);
 #pragma unroll
             for (int t = 0; t < QT; ++t) {
-                const real a = frag(OFF_VQ + t * SP + s);
+                const real a = fragq(t, s);
                 VF[t] = M::run(a, bf, VF[t]);
                 VP[t] = M::run(a, bpv, VP[t]);
             }
@@ -332,7 +403,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 if (sq < SQ) {
 #pragma unroll
                     for (int t = 0; t < PT; ++t) {
-                        const real a = frag(OFF_PQ + t * SQM + sq);
+                        const real a = frag(OFF_PQ, t, sq, SQM);
                         RP[t] = M::run(a, VP[tq][v], RP[t]);
                         R[t] = M::run(a, VF[tq][v], R[t]);
                     }
@@ -381,7 +452,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 const int sp = 4 * tp + v;
                 if (sp < SP) {
 #pragma unroll
-                    for (int t = 0; t < QT; ++t) Z[t] = M::run(frag(OFF_VQ + t * SP + sp), R[tp][v], Z[t]);
+                    for (int t = 0; t < QT; ++t) Z[t] = M::run(fragq(t, sp), R[tp][v], Z[t]);
                 }
             }
         if (KAPPA) {
@@ -407,7 +478,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
                 const int sq = 4 * tq + v;
                 if (sq < SQ) {
 #pragma unroll
-                    for (int t = 0; t < PT; ++t) O[t] = M::run(frag(OFF_PQ + t * SQM + sq), Z[tq][v], O[t]);
+                    for (int t = 0; t < PT; ++t) O[t] = M::run(frag(OFF_PQ, t, sq, SQM), Z[tq][v], O[t]);
                 }
             }
 #pragma unroll
@@ -431,7 +502,7 @@ __global__ __launch_bounds__(kMfmaThreads) void stage_mfma_kernel(StageParams p)
 
 template <typename real, int N, int QT, bool K>
 int launch_t(const StageParams& p, hipStream_t s) {
-    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K>), dim3(4 * p.nblk), dim3(kMfmaThreads), 0, s, p);
+    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K>), dim3(4 / kMfmaTiles * p.nblk), dim3(kMfmaTiles * kMfmaThreads), 0, s, p);
     return static_cast<int>(hipGetLastError());
 }
 
