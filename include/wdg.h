@@ -224,6 +224,53 @@ int32_t wdg_element_info(const wdg_ctx* ctx, double* J, double* Fscale, double* 
 
 int32_t wdg_memory_report(const wdg_ctx* ctx, wdg_mem_t* out);
 
+/* ---- Conductivity at the cubature points and differentiation ------------- */
+
+/* sigma_u at the cubature points of every element (eqs. (9), (19)-(21): the PML
+ * enters the scheme only through these samples), double [K][nq][3] in user
+ * element order.  get returns the current values (zero outside the PML).  set
+ * replaces them: values must be finite and zero on elements outside the PML
+ * (they carry no auxiliary fields); WDG_EINVAL otherwise.  kappa is unchanged.
+ * The arrays are copied. */
+int32_t wdg_set_sigma_q(wdg_ctx* ctx, const double* sigma);
+int32_t wdg_get_sigma_q(const wdg_ctx* ctx, double* sigma);
+
+/* Physical cubature points double [K][nq][3], user element order. */
+int32_t wdg_cubature_points(const wdg_ctx* ctx, double* xyz);
+
+/* Axis-aligned shell: the points of the closed box [outer_lo, outer_hi] that
+ * are not in the open box (inner_lo, inner_hi). */
+typedef struct wdg_shell {
+    double outer_lo[3], outer_hi[3];
+    double inner_lo[3], inner_hi[3];
+} wdg_shell;
+
+/* Shell energy of the current fields in cubature form,
+ * 1/2 sum_k J_k sum_q w_q chi(x_kq) (|E|^2 + |H|^2) at the cubature points
+ * (fields interpolated with V_q, eq. (20)), accumulated in FP64.  Synchronises
+ * hip_stream.  WDG_ENONFINITE if not finite. */
+int32_t wdg_shell_energy(wdg_ctx* ctx, const wdg_shell* shell, double* out, void* hip_stream);
+
+/* Loss J = sum_{n=1..nsteps} dt * shell_energy(q_n) over nsteps LSERK4 steps of
+ * size dt from the current state, and its gradient from the discrete adjoint
+ * of the scheme (energy inner product; the vacuum operator's adjoint is the
+ * operator with the flux parameter negated, the PML terms of eqs. (26)-(29)
+ * are transposed):
+ *   grad_sigma   double [K][nq][3]: dJ/dsigma at the cubature points, zero
+ *                outside the PML (NULL: not returned);
+ *   grad_profile double [7]: dJ/d(sigma_max x,y,z, L x,y,z, profile order) of
+ *                the profile given at creation, with the outer wall fixed and
+ *                the interface moving with L (NULL: not returned).
+ * The state advances by nsteps steps exactly as with wdg_step (no probe rows).
+ * Forward states are checkpointed every checkpoint_interval steps (0:
+ * ceil(sqrt(nsteps))); device memory for ceil(nsteps / interval) + 5 interval
+ * + 6 state buffers is allocated and freed inside the call.  Needs kappa = 1
+ * and an order and rule with a matrix-core kernel (WDG_EINVAL otherwise: FP64
+ * at N = 4, N = 3 with more than 32 cubature points in FP64).  Synchronous. */
+int32_t wdg_loss_gradient(wdg_ctx* ctx, double dt, int32_t nsteps, const wdg_shell* shell,
+                          int32_t checkpoint_interval, double* loss, double* grad_sigma,
+                          double* grad_profile, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

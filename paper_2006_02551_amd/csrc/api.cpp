@@ -11,68 +11,21 @@
 #include <vector>
 
 #include "../../include/wdg.h"
-#include "device.hpp"
-#include "host.hpp"
+#include "context.hpp"
 
 using namespace wdg;
 
 namespace {
-
-// LSERK4 coefficients (Carpenter & Kennedy 1994, five-stage 2N-storage,
-// fourth order), as the published rationals.
-const double kRkA[5] = {0.0,
-                        -567301805773.0 / 1357537059087.0,
-                        -2404267990393.0 / 2016746695238.0,
-                        -3550918686646.0 / 2091501179385.0,
-                        -1275806237668.0 / 842570457699.0};
-const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
-                        5161836677717.0 / 13612068292357.0,
-                        1720146321549.0 / 2090206949498.0,
-                        3134564353537.0 / 4481467310338.0,
-                        2277821191437.0 / 14882151754819.0};
-const double kRkC[5] = {0.0,
-                        1432997174477.0 / 9575080441755.0,
-                        2526269341429.0 / 6820363962896.0,
-                        2006345519317.0 / 3224310063776.0,
-                        2802321613138.0 / 2924317926251.0};
-
 thread_local std::string g_create_error;
+}  // namespace
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    void alloc(size_t n) {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = n;
-        if (n == 0) return;
-        const hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            throw Error(WDG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-        }
-    }
-    void upload(const void* src, size_t n) {
-        alloc(n);
-        if (n == 0) return;
-        const hipError_t e = hipMemcpy(p, src, n, hipMemcpyHostToDevice);
-        if (e != hipSuccess) throw Error(WDG_EHIP, std::string("hipMemcpy failed: ") + hipGetErrorString(e));
-    }
-};
+namespace wdg {
 
 void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) throw Error(WDG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename T>
-std::vector<unsigned char> as_real(const std::vector<double>& v, int precision) {
-    (void)sizeof(T);
+std::vector<unsigned char> to_real(const std::vector<double>& v, int precision) {
     std::vector<unsigned char> out;
     if (precision == WDG_FP64) {
         out.resize(v.size() * sizeof(double));
@@ -85,40 +38,6 @@ std::vector<unsigned char> as_real(const std::vector<double>& v, int precision) 
     return out;
 }
 
-std::vector<unsigned char> to_real(const std::vector<double>& v, int precision) { return as_real<double>(v, precision); }
-
-}  // namespace
-
-struct wdg_ctx {
-    Setup S;
-    int precision = WDG_FP64;
-    bool host_only = false;
-    std::string err;
-    int device = 0;
-    size_t rsize = 8;
-    int64_t state_elems = 0;
-    // device setup
-    DevBuf geo, nbr, sigma, kappa, ops, fmask, Jk, Mref, partial, scalar_out;
-    DevBuf src_slot, src;
-    DevBuf frags;
-    bool mfma_ok = false;
-    int kernel = WDG_KERNEL_SCALAR;
-    bool has_src = false;
-    wdg_dipole dip{};
-    // probes
-    int nprobe = 0, probe_cap = 0, probe_rows = 0;
-    DevBuf probe_slot, probe_w, probe_buf;
-    // state
-    void* q[2] = {nullptr, nullptr};
-    void* res = nullptr;
-    int cur = 0;
-    double t = 0.0;
-    int64_t steps = 0;
-    size_t off_DrT = 0, off_DsT = 0, off_DtT = 0, off_LIFTT = 0, off_Vq = 0, off_PqT = 0;
-};
-
-namespace {
-
 int fail(wdg_ctx* ctx, int code, const std::string& msg) {
     if (ctx)
         ctx->err = msg;
@@ -127,22 +46,6 @@ int fail(wdg_ctx* ctx, int code, const std::string& msg) {
     return code;
 }
 
-template <typename F>
-int guarded(wdg_ctx* ctx, F&& fn) {
-    try {
-        return fn();
-    } catch (const Error& e) {
-        return fail(ctx, e.code, e.what());
-    } catch (const std::bad_alloc&) {
-        return fail(ctx, WDG_ENOMEM, "host allocation failed");
-    } catch (const std::exception& e) {
-        return fail(ctx, WDG_EINVAL, e.what());
-    }
-}
-
-int64_t eh_words(const Setup& S) { return static_cast<int64_t>(6) * S.ref.Np * S.B; }
-
-// Offset of (user element k, canonical component c, node i) in the blocked buffer, or -1.
 int64_t state_index(const Setup& S, int k, int c, int i) {
     const int slot = S.perm[k];
     const int blk = slot / S.B, lane = slot % S.B;
@@ -151,6 +54,39 @@ int64_t state_index(const Setup& S, int k, int c, int i) {
     if (!S.is_pml[k]) return -1;
     return static_cast<int64_t>(S.nblk) * ehs + blk * ehs + (static_cast<int64_t>(c - 6) * S.ref.Np + i) * S.B + lane;
 }
+
+}  // namespace wdg
+
+namespace {
+
+}  // namespace
+
+namespace wdg {
+
+void upload_coefficients(wdg_ctx* c) {
+    const Setup& S = c->S;
+    const int Nq = S.ref.Nq, B = S.B, nblk_pml = S.nblk_pml;
+    // sigma (and kappa) at cubature points, PML blocks only
+    std::vector<double> sg(static_cast<size_t>(std::max(nblk_pml, 1)) * 3 * Nq * B, 0.0);
+    std::vector<double> kp(S.has_kappa ? sg.size() : 0, 1.0);
+    for (int slot = 0; slot < nblk_pml * B; ++slot) {
+        const int k = S.slot_elem[slot];
+        if (k < 0) continue;
+        const int blk = slot / B, lane = slot % B;
+        for (int d = 0; d < 3; ++d)
+            for (int q = 0; q < Nq; ++q) {
+                const size_t di = ((static_cast<size_t>(blk) * 3 + d) * Nq + q) * B + lane;
+                sg[di] = S.sigma[(static_cast<size_t>(k) * Nq + q) * 3 + d];
+                if (S.has_kappa) kp[di] = S.kappa[(static_cast<size_t>(k) * Nq + q) * 3 + d];
+            }
+    }
+    c->sigma.upload(to_real(sg, c->precision).data(), sg.size() * c->rsize);
+    if (S.has_kappa) c->kappa.upload(to_real(kp, c->precision).data(), kp.size() * c->rsize);
+}
+
+}  // namespace wdg
+
+namespace {
 
 void upload_setup(wdg_ctx* c) {
     const Setup& S = c->S;
@@ -195,22 +131,7 @@ void upload_setup(wdg_ctx* c) {
     c->nbr.upload(nbr.data(), nbr.size() * sizeof(int));
     c->Jk.upload(Jk.data(), Jk.size() * sizeof(double));
 
-    // sigma (and kappa) at cubature points, PML blocks only
-    std::vector<double> sg(static_cast<size_t>(std::max(nblk_pml, 1)) * 3 * Nq * B, 0.0);
-    std::vector<double> kp(S.has_kappa ? sg.size() : 0, 1.0);
-    for (int slot = 0; slot < nblk_pml * B; ++slot) {
-        const int k = S.slot_elem[slot];
-        if (k < 0) continue;
-        const int blk = slot / B, lane = slot % B;
-        for (int d = 0; d < 3; ++d)
-            for (int q = 0; q < Nq; ++q) {
-                const size_t di = ((static_cast<size_t>(blk) * 3 + d) * Nq + q) * B + lane;
-                sg[di] = S.sigma[(static_cast<size_t>(k) * Nq + q) * 3 + d];
-                if (S.has_kappa) kp[di] = S.kappa[(static_cast<size_t>(k) * Nq + q) * 3 + d];
-            }
-    }
-    c->sigma.upload(to_real(sg, c->precision).data(), sg.size() * c->rsize);
-    if (S.has_kappa) c->kappa.upload(to_real(kp, c->precision).data(), kp.size() * c->rsize);
+    upload_coefficients(c);
 
     // operators packed in one buffer
     std::vector<double> ops;
@@ -269,6 +190,7 @@ void upload_setup(wdg_ctx* c) {
         c->kernel = WDG_KERNEL_MFMA;
     }
     c->fmask.upload(R.fmask.data(), R.fmask.size() * sizeof(int));
+    c->cubw.upload(R.wq.data(), R.wq.size() * sizeof(double));
     c->Mref.upload(R.M.data(), R.M.size() * sizeof(double));
     c->partial.alloc(static_cast<size_t>(nblk) * sizeof(double));
     c->scalar_out.alloc(sizeof(double));
@@ -276,17 +198,17 @@ void upload_setup(wdg_ctx* c) {
     c->src_slot.upload(slots.data(), slots.size() * sizeof(int));
 }
 
-const char* cptr(const DevBuf& b, size_t off_words, size_t rsize) {
-    return static_cast<const char*>(b.p) + off_words * rsize;
-}
+}  // namespace
 
-int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, double rk_a, double rk_b, double dt, double t,
+namespace wdg {
+
+int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double rk_a, double rk_b, double dt, double t,
                     bool read_res, hipStream_t stream) {
     const Setup& S = c->S;
     StageParams p{};
     p.q_in = qin;
     p.q_out = qout;
-    p.res = c->res;
+    p.res = res;
     p.geo = c->geo.p;
     p.nbr = static_cast<const int*>(c->nbr.p);
     p.sigma = c->sigma.p;
@@ -327,7 +249,7 @@ int check_state(wdg_ctx* c) {
     return WDG_OK;
 }
 
-}  // namespace
+}  // namespace wdg
 
 extern "C" {
 
@@ -601,7 +523,7 @@ int32_t wdg_step(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) {
     return guarded(c, [&]() -> int {
         for (int n = 0; n < nsteps; ++n) {
             for (int i = 0; i < 5; ++i) {
-                const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], kRkA[i], kRkB[i], dt,
+                const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[i], kRkB[i], dt,
                                                c->t + kRkC[i] * dt, i > 0, s);
                 if (rc != WDG_OK) return rc;
                 c->cur = 1 - c->cur;
@@ -630,7 +552,7 @@ int32_t wdg_rhs(wdg_ctx* c, double t, void* hip_stream) {
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     return guarded(c, [&]() -> int {
         // res = 0 * res + 1 * rhs, q_out = q_in + 0 * res into the spare buffer
-        return launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], 0.0, 0.0, 1.0, t, false, s);
+        return launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, 0.0, 0.0, 1.0, t, false, s);
     });
 }
 

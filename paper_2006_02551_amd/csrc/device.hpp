@@ -59,9 +59,42 @@ struct StageParams {
     const int* src_slot;  // [nblk] source slot of a block or -1
     const void* src;      // [nslot][3][Np][B] J direction times spatial factor
     const void* frags;    // MFMA kernel: operator A fragments (V_q, P_q, D_r, D_s, D_t, LIFT)
+    // adjoint stage only
+    const void* q_base;   // running adjoint (the update's base)
+    const void* q_fwd;    // forward stage input (for the sigma gradient)
+    double* grad;         // [nblk_pml][3][Nq][B] sigma gradient accumulator (FP64)
+    const double* cub_w;  // [Nq] cubature weights
+    const double* Jk;     // [nblk][B] Jacobians
     int nblk_pml, nblk, Nq;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
+};
+
+// Adjoint stage preparation: y <- a_next y + b q_hat (a_next = 0 drops the old
+// y), z = P_q V_q y_f on PML blocks (kappa = 1), z = y_f elsewhere.
+struct PrepParams {
+    void* y;              // stage adjoint, state layout, updated in place
+    const void* q_hat;    // running adjoint, state layout
+    void* z;              // [nblk][6][Np][B]
+    const void* Vq;       // [Nq][Np]
+    const void* PqT;      // [Nq][Np]
+    int nblk_pml, nblk, Nq;
+    double a_next, b;
+};
+
+// Shell-energy loss and its gradient on the blocks holding shell points.
+struct ShellParams {
+    const void* q;        // state the energy is taken of
+    void* q_hat;          // running adjoint (gradient injection)
+    const int* blocks;    // [nsb] block of each shell block
+    const void* chi;      // [nsb][Nq][B] shell indicator at the cubature points
+    const double* Jk;     // [nblk][B]
+    const double* cub_w;  // [Nq]
+    const void* Vq;       // [Nq][Np]
+    const void* PqT;      // [Nq][Np]
+    double* partial;      // [nsb]
+    int nsb, nblk, Nq;
+    double dt;
 };
 
 struct ProbeParams {
@@ -83,8 +116,18 @@ struct EnergyParams {
 // Launchers (kernels.hip, kernels_mfma.hip); return hipError_t as int.
 int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
 int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+// Adjoint stage on the matrix cores (kappa = 1; same (N, N_q) support as the forward).
+int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s);
 bool mfma_supported(int N, int Nq, int precision);
+bool adjoint_supported(int N, int Nq, int precision);
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
+int launch_adjoint_prep(int precision, int N, const PrepParams& p, hipStream_t s);
+// partial[sb] = sum over the block's slots of J w_q chi (V_q u)^2 over the six E,H components
+int launch_shell_energy(int precision, int N, const ShellParams& p, hipStream_t s);
+// *acc += scale * sum(partial[0..n)) in a fixed order (one workgroup)
+int launch_sum_into(const double* partial, int n, double scale, double* acc, hipStream_t s);
+// q_hat += dt P_q (chi V_q u) for the six E,H components on the shell blocks
+int launch_shell_inject(int precision, int N, const ShellParams& p, hipStream_t s);
 int launch_energy(int precision, int N, const EnergyParams& p, double* out, hipStream_t s);
 
 }  // namespace wdg

@@ -68,6 +68,8 @@ struct Setup {
     std::vector<int> nbr_node;           // [K][4][Nfp] neighbour volume node (or own node at walls)
     std::vector<double> xnodes;          // [K][Np][3]
     std::vector<double> sigma, kappa;    // [K][Nq][3]
+    std::vector<double> xq;              // [K][Nq][3] physical cubature points
+    PmlParams pml{};                     // the profile sigma and kappa were sampled from
     std::vector<int> is_pml;             // [K]
     // device ordering
     std::vector<int> perm;               // user element -> slot (blk*B + lane)

@@ -101,7 +101,7 @@ constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
 
 // Compile-time shape of the kernel for one precision, order and number of
 // cubature tiles.
-template <typename real, int N, int QT>
+template <typename real, int N, int QT, bool ADJ = false>
 struct Shape {
     static constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, T = 16;
     static constexpr int NF = 4 * Nfp;             // face nodes per element
@@ -131,19 +131,28 @@ struct Shape {
     static constexpr int L_NB = pad1k(NF * T * 4);
     static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
     static constexpr int L_FL = 6 * NFH * T * RB;
-    static constexpr int LDS = L_FR + kMfmaTiles * (L_TL + L_FL);
+    static constexpr int L_GL = ADJ ? 3 * QMAX * T * RB : 0;  // adjoint: sigma-gradient accumulator
+    static constexpr int LDS = L_FR + kMfmaTiles * (L_TL + L_FL + L_GL);
     // Two workgroups per compute unit (6 wavefronts per SIMD) where their LDS
     // fits in the 160 KiB of a compute unit; the compiler then keeps the
     // registers to that occupancy.
     static constexpr int WAVES_PER_SIMD = 2 * LDS <= 160 * 1024 ? 6 : 1;
 };
 
-template <typename real, int N, int QT, bool KAPPA>
-__global__ __launch_bounds__(kMfmaTiles * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT>::WAVES_PER_SIMD)))
+// ADJ selects the adjoint stage (the energy-inner-product transpose of the
+// stage operator; kappa = 1): q_in holds z (the weight-adjusted adjoint of the
+// fields), res the stage adjoint y, q_base the running adjoint; the kernel
+// writes q_base + dt L* y to q_out and adds the stage's sigma gradient to
+// p.grad.  Same staging, flux, lift and curl as the forward stage, with the
+// flux parameter negated by the caller.
+template <typename real, int N, int QT, bool KAPPA, bool ADJ>
+__global__ __launch_bounds__(kMfmaTiles * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ>::WAVES_PER_SIMD)))
 void stage_mfma_kernel(StageParams p) {
+    static_assert(!(ADJ && KAPPA), "the adjoint stage is written for kappa = 1");
     using M = Mma<real>;
     using v4 = typename M::v4;
-    using S = Shape<real, N, QT>;
+    using S = Shape<real, N, QT, ADJ>;
+    constexpr int QMAX = S::QMAX;
     constexpr int Np = S::Np, Nfp = S::Nfp, B = kBlock, T = S::T;
     constexpr int NF = S::NF, PT = S::PT, MR = S::MR, SP = S::SP, SQM = S::SQM, SF = S::SF, S0 = S::S0;
     constexpr bool F64 = sizeof(real) == 8;
@@ -155,6 +164,7 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int L_FR = S::L_FR, L_EH = S::L_EH, L_SG = S::L_SG, L_GE = S::L_GE, L_TL = S::L_TL;
     __shared__ __attribute__((aligned(16))) char smem[L_FR + kMfmaTiles * L_TL];
     __shared__ real fls[kMfmaTiles][6 * NFH * T];  // flux [component][face node of the round][element of the tile]
+    __shared__ real gls[ADJ ? kMfmaTiles * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
 
     // Workgroup: kMfmaTiles adjacent tiles of one element block, six
     // wavefronts each (a multiple of four wavefronts keeps the four SIMDs of a
@@ -179,6 +189,11 @@ void stage_mfma_kernel(StageParams p) {
     const int g = lane >> 4, j = lane & 15;
     const int e = T * sub + j;
     const real* __restrict__ qin = static_cast<const real*>(p.q_in);
+
+    real* gl = gls + (ADJ ? h * 3 * QMAX * T : 0);
+    if constexpr (ADJ) {
+        for (int i = tid; i < 3 * QMAX * T; i += kMfmaThreads) gl[i] = real(0);
+    }
 
     // ---- stage the tile into LDS (direct global->LDS loads)
     {
@@ -228,16 +243,20 @@ void stage_mfma_kernel(StageParams p) {
     // ---- per-wave loads that only this wave needs, issued to overlap the flux phase
     const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
     const size_t ebase = static_cast<size_t>(blk) * EHS + e;
-    real* __restrict__ rs = static_cast<real*>(p.res);
+    real* __restrict__ rs = static_cast<real*>(p.res);  // forward: residual; adjoint: stage adjoint y (read only)
     real* __restrict__ qo = static_cast<real*>(p.q_out);
+    // base of the update (forward: q_in; adjoint: the running adjoint) and the
+    // auxiliary fields entering the PML terms (forward: q_in; adjoint: y)
+    const real* __restrict__ qb = ADJ ? static_cast<const real*>(p.q_base) : qin;
+    const real* __restrict__ pin = ADJ ? static_cast<const real*>(p.res) : qin;
     const bool read_res = p.read_res != 0;
     real bp[SP];
-    real rP[PT][4], qP[PT][4], rE[PT][4];
+    real rP[PT][4], qP[PT][4], rE[PT][4];  // adjoint: rE holds the E,H base, rP is unused
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
         const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-        bp[s] = pml ? qin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+        bp[s] = pml ? pin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
     }
 #pragma unroll
     for (int t = 0; t < PT; ++t)
@@ -245,10 +264,24 @@ void stage_mfma_kernel(StageParams p) {
         for (int v = 0; v < 4; ++v) {
             const int node = 16 * t + 4 * v + g;
             const int nd = node < Np ? node : 0;
-            rP[t][v] = (pml && read_res) ? rs[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-            qP[t][v] = pml ? qin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-            rE[t][v] = read_res ? rs[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            rP[t][v] = (!ADJ && pml && read_res) ? rs[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            qP[t][v] = pml ? qb[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            rE[t][v] = ADJ ? qb[ebase + static_cast<size_t>(u * Np + nd) * B]
+                           : (read_res ? rs[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0));
         }
+    // adjoint: this component's forward fields at the stage input, for the sigma gradient
+    constexpr int SPA = ADJ ? SP : 1;
+    real ff[SPA], fp[SPA];
+    if constexpr (ADJ) {
+        const real* __restrict__ qf = static_cast<const real*>(p.q_fwd);
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+            const int node = 4 * s + g;
+            const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
+            ff[s] = pml ? qf[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            fp[s] = pml ? qf[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+        }
+    }
 
     // Fragment word of lane `lane` for operator tile t (of nt) and k-step s (of K k-steps).
     const int lq = F64 ? (lane & 15) : 4 * (lane & 3) + ((lane & 15) >> 2);
@@ -345,9 +378,14 @@ void stage_mfma_kernel(StageParams p) {
     if (pml) {
         const real* __restrict__ kp =
             KAPPA ? static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + e : nullptr;
-        v4 VF[QT], VP[QT];
+        // forward: VF = V_q f_u, VP = V_q P_u; adjoint: VF = V_q z_u, VP = V_q y_{P,u}
+        // and, for the gradient, VFf = V_q f_u, VPf = V_q P_u of the forward stage input
+        constexpr int QTA = ADJ ? QT : 1;
+        v4 VF[QT], VP[QT], VFf[QTA], VPf[QTA];
 #pragma unroll
         for (int t = 0; t < QT; ++t) VF[t] = VP[t] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < QTA; ++t) VFf[t] = VPf[t] = v4{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
             const int node = 4 * s + g;
@@ -359,9 +397,18 @@ void stage_mfma_kernel(StageParams p) {
                 const real a = fragq(t, s);
                 VF[t] = M::run(a, bf, VF[t]);
                 VP[t] = M::run(a, bpv, VP[t]);
+                if constexpr (ADJ) {
+                    VFf[t] = M::run(a, ok ? ff[s] : real(0), VFf[t]);
+                    VPf[t] = M::run(a, ok ? fp[s] : real(0), VPf[t]);
+                }
             }
         }
-        // eq. (9) at cubature point q = 16 t + 4 v + g: VF <- -t1, VP <- t2
+        // eq. (9) at cubature point q = 16 t + 4 v + g.  Forward: VF <- -t1,
+        // VP <- t2.  Adjoint: VF <- b VZ - kappa^-1 VY, VP <- -c VZ - d VY, and
+        // the node's sigma gradient (kappa = 1: db/dsigma_(u,v,w) = (-1, 1, 1),
+        // dc/dsigma_(u,v,w) = (sigma_u - b, sigma_w - sigma_u, sigma_v - sigma_u),
+        // dd/dsigma_u = 1) goes to the LDS accumulator, weighted by dt J w_q.
+        const double wJ = ADJ ? p.dt * p.Jk[static_cast<size_t>(blk) * B + e] : 0.0;
 #pragma unroll
         for (int t = 0; t < QT; ++t)
 #pragma unroll
@@ -385,8 +432,21 @@ void stage_mfma_kernel(StageParams p) {
                         dq = sa;
                     }
                     const real vf = VF[t][v], vp = VP[t][v];
-                    t1 = bq * vf + cq * vp;
-                    t2 = kinv * vf - dq * vp;
+                    if constexpr (ADJ) {
+                        const real vff = VFf[t][v], vpf = VPf[t][v];
+                        const real w = static_cast<real>(wJ * p.cub_w[q]);
+                        const real gu = -vf * (-vff + (sa - bq) * vpf) - vp * vpf;
+                        const real gv = -vf * (vff + (scq - sa) * vpf);
+                        const real gw = -vf * (vff + (sbq - sa) * vpf);
+                        atomicAdd(&gl[(ax * QMAX + q) * T + j], w * gu);
+                        atomicAdd(&gl[(bb * QMAX + q) * T + j], w * gv);
+                        atomicAdd(&gl[(cc * QMAX + q) * T + j], w * gw);
+                        t1 = kinv * vp - bq * vf;
+                        t2 = -cq * vf - dq * vp;
+                    } else {
+                        t1 = bq * vf + cq * vp;
+                        t2 = kinv * vf - dq * vp;
+                    }
                 }
                 VF[t][v] = -t1;
                 VP[t][v] = t2;
@@ -417,15 +477,19 @@ void stage_mfma_kernel(StageParams p) {
                 const int node = 16 * t + 4 * v + g;
                 if (node < Np) {
                     const size_t idx = pbase + static_cast<size_t>(u * Np + node) * B;
-                    const real r = dt * RP[t][v] + rkA * rP[t][v];
-                    rs[idx] = r;
-                    qo[idx] = qP[t][v] + rkB * r;
+                    if constexpr (ADJ) {
+                        qo[idx] = qP[t][v] + dt * RP[t][v];
+                    } else {
+                        const real r = dt * RP[t][v] + rkA * rP[t][v];
+                        rs[idx] = r;
+                        qo[idx] = qP[t][v] + rkB * r;
+                    }
                 }
             }
     }
 
-    // ---- dipole source on the electric components
-    if (u < 3) {
+    // ---- dipole source on the electric components (not part of the adjoint operator)
+    if (!ADJ && u < 3) {
         const int slot = p.src_slot[blk];
         if (slot >= 0) {
             const real gsrc = static_cast<real>(p.src_g);
@@ -440,8 +504,9 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
-    // ---- D. weight-adjusted inverse mass on PML tiles: rhs = P_q a^-1 V_q R (eq. (21))
-    if (pml) {
+    // ---- D. weight-adjusted inverse mass on PML tiles: rhs = P_q a^-1 V_q R (eq. (21));
+    // in the adjoint it acts before the curl (on y, giving z)
+    if (!ADJ && pml) {
         v4 Z[QT];
 #pragma unroll
         for (int t = 0; t < QT; ++t) Z[t] = v4{0, 0, 0, 0};
@@ -493,22 +558,61 @@ void stage_mfma_kernel(StageParams p) {
             const int node = 16 * t + 4 * v + g;
             if (node < Np) {
                 const size_t idx = ebase + static_cast<size_t>(u * Np + node) * B;
-                const real r = dt * R[t][v] + rkA * rE[t][v];
-                rs[idx] = r;
-                qo[idx] = ehv(u, node) + rkB * r;
+                if constexpr (ADJ) {
+                    // L* y = -L_vac(-alpha) z + P_q(-b VZ + kappa^-1 VY) = -R
+                    qo[idx] = rE[t][v] - dt * R[t][v];
+                } else {
+                    const real r = dt * R[t][v] + rkA * rE[t][v];
+                    rs[idx] = r;
+                    qo[idx] = ehv(u, node) + rkB * r;
+                }
             }
         }
+
+    // ---- adjoint: add the tile's sigma gradient (all six components summed) to p.grad
+    if constexpr (ADJ) {
+        if (pml) {
+            __syncthreads();
+            double* __restrict__ gd = p.grad + static_cast<size_t>(blk) * 3 * Nq * B + T * sub;
+            for (int i = tid; i < 3 * Nq * T; i += kMfmaThreads) {
+                const int jj = i & (T - 1), aq = i >> 4;  // aq = axis * Nq + q
+                const int a = aq / Nq, q = aq - a * Nq;
+                gd[static_cast<size_t>(aq) * B + jj] += static_cast<double>(gl[(a * QMAX + q) * T + jj]);
+            }
+        }
+    }
 }
 
-template <typename real, int N, int QT, bool K>
+template <typename real, int N, int QT, bool K, bool ADJ = false>
 int launch_t(const StageParams& p, hipStream_t s) {
-    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K>), dim3(4 / kMfmaTiles * p.nblk), dim3(kMfmaTiles * kMfmaThreads), 0, s, p);
-    return static_cast<int>(hipGetLastError());
+    if constexpr (Shape<real, N, QT, ADJ>::LDS > 160 * 1024) {
+        return static_cast<int>(hipErrorInvalidConfiguration);  // more LDS than a compute unit has
+    } else {
+        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ>), dim3(4 / kMfmaTiles * p.nblk),
+                           dim3(kMfmaTiles * kMfmaThreads), 0, s, p);
+        return static_cast<int>(hipGetLastError());
+    }
 }
+
+template <typename real, int N, int QT>
+constexpr bool adj_fits() { return Shape<real, N, QT, true>::LDS <= 160 * 1024; }
 
 template <typename real, int N, int QT>
 int launch_k(bool k, const StageParams& p, hipStream_t s) {
     return k ? launch_t<real, N, QT, true>(p, s) : launch_t<real, N, QT, false>(p, s);
+}
+
+template <typename real>
+int launch_adj(int N, int QT, const StageParams& p, hipStream_t s) {
+    switch (N * 10 + QT) {
+        case 11: return launch_t<real, 1, 1, false, true>(p, s);
+        case 12: return launch_t<real, 1, 2, false, true>(p, s);
+        case 21: return launch_t<real, 2, 1, false, true>(p, s);
+        case 22: return launch_t<real, 2, 2, false, true>(p, s);
+        case 32: return launch_t<real, 3, 2, false, true>(p, s);
+        case 33: return launch_t<real, 3, 3, false, true>(p, s);
+        default: return -1;
+    }
 }
 
 // Order / cubature-tile combinations with a matrix-core kernel.  FP64 at
@@ -536,6 +640,23 @@ int launch_r4(int QT, bool k, const StageParams& p, hipStream_t s) {
 
 }  // namespace
 
+bool adjoint_supported(int N, int Nq, int precision) {
+    if (!mfma_supported(N, Nq, precision)) return false;
+    const int QT = (Nq + 15) / 16;
+    const bool f64 = precision == 0;
+    switch (N * 10 + QT) {
+        case 11: return f64 ? adj_fits<double, 1, 1>() : adj_fits<float, 1, 1>();
+        case 12: return f64 ? adj_fits<double, 1, 2>() : adj_fits<float, 1, 2>();
+        case 21: return f64 ? adj_fits<double, 2, 1>() : adj_fits<float, 2, 1>();
+        case 22: return f64 ? adj_fits<double, 2, 2>() : adj_fits<float, 2, 2>();
+        case 32: return f64 ? adj_fits<double, 3, 2>() : adj_fits<float, 3, 2>();
+        case 33: return f64 ? adj_fits<double, 3, 3>() : adj_fits<float, 3, 3>();
+        case 43: return !f64 && adj_fits<float, 4, 3>();
+        case 44: return !f64 && adj_fits<float, 4, 4>();
+        default: return false;
+    }
+}
+
 bool mfma_supported(int N, int Nq, int precision) {
     const int QT = (Nq + 15) / 16;
     switch (N * 10 + QT) {
@@ -543,6 +664,13 @@ bool mfma_supported(int N, int Nq, int precision) {
         case 43: case 44: return precision != 0;
         default: return false;
     }
+}
+
+int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s) {
+    const int QT = (p.Nq + 15) / 16;
+    if (N == 4) return precision == 0 ? -1 : (QT == 3 ? launch_t<float, 4, 3, false, true>(p, s)
+                                                      : QT == 4 ? launch_t<float, 4, 4, false, true>(p, s) : -1);
+    return precision == 0 ? launch_adj<double>(N, QT, p, s) : launch_adj<float>(N, QT, p, s);
 }
 
 int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s) {

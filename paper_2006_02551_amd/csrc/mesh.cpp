@@ -234,6 +234,8 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
     S.kappa.assign(static_cast<size_t>(K) * Nq * 3, 1.0);
     S.is_pml.assign(K, 0);
     S.has_kappa = pml.kappa_max != 1.0;
+    S.xq.assign(static_cast<size_t>(K) * Nq * 3, 0.0);
+    S.pml = pml;
     for (int k = 0; k < K; ++k) {
         const int* ev = &S.etov[4 * static_cast<size_t>(k)];
         const double* v0 = &S.vxyz[3 * static_cast<size_t>(ev[0])];
@@ -245,6 +247,7 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
             const double rr = R.rq[q] + 1.0, ss = R.sq[q] + 1.0, tt = R.tq[q] + 1.0;
             for (int d = 0; d < 3; ++d) {
                 const double x = v0[d] + 0.5 * ((v1[d] - v0[d]) * rr + (v2[d] - v0[d]) * ss + (v3[d] - v0[d]) * tt);
+                S.xq[(static_cast<size_t>(k) * Nq + q) * 3 + d] = x;
                 const double ratio = profile_ratio(x, pml.lo[d], pml.hi[d], pml.L[d], pml.order);
                 const double sg = pml.sigma_max[d] * ratio;
                 const double kp = 1.0 + (pml.kappa_max - 1.0) * ratio;

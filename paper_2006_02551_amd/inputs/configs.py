@@ -19,6 +19,7 @@ Each recipe is a plain dict:
               * exp(-|x-center|^2/width^2) * direction
   probes      probe points [n, 3] (or None)
   steps       number of LSERK4 steps
+  shell       (differentiation form) box shell of the loss: outer_lo/hi, inner_lo/hi
   cfl         dt = cfl / ((N+1)^2 * max_{k,f} Fscale_{k,f})
 """
 from __future__ import annotations
@@ -61,6 +62,16 @@ CONFIGS = {
            "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [40.0] * 3,
                    "order": 2.0, "kappa_max": 1.0},
            "alpha": 1.0, "init": None, "source": _DIPOLE, "probes": _CUBE8, "steps": 2000, "cfl": CFL},
+    # Differentiation form: the 48,000-tet N=3 mesh and cubic profile of c2, a Gaussian Ez pulse at the
+    # origin that reaches the layer within the 500 steps, loss = time-integrated energy in the shell
+    # 0.1 inside the PML interface.
+    "c5": {"name": "c5", "N": 3, "cub_degree": 6,
+           "mesh": {"n": 20, "lo": -1.5, "hi": 1.5, "perturb": 0.1, "seed": 0},
+           "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [30.0] * 3,
+                   "order": 3.0, "kappa_max": 1.0},
+           "alpha": 1.0, "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.25},
+           "source": None, "probes": None, "steps": 500, "cfl": CFL,
+           "shell": {"outer_lo": [-1.0] * 3, "outer_hi": [1.0] * 3, "inner_lo": [-0.9] * 3, "inner_hi": [0.9] * 3}},
 }
 
 

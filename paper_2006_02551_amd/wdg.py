@@ -74,6 +74,11 @@ class wdg_mem_t(C.Structure):
 _ctx = C.c_void_p
 
 
+class wdg_shell(C.Structure):
+    _fields_ = [("outer_lo", C.c_double * 3), ("outer_hi", C.c_double * 3),
+                ("inner_lo", C.c_double * 3), ("inner_hi", C.c_double * 3)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -103,6 +108,12 @@ wdg_node_coords = _sig("wdg_node_coords", C.c_int32, _ctx, _dp)
 wdg_reference_op = _sig("wdg_reference_op", C.c_int32, _ctx, C.c_int32, _dp)
 wdg_element_info = _sig("wdg_element_info", C.c_int32, _ctx, _dp, _dp, _dp, _ip, _ip, _ip)
 wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem_t))
+wdg_set_sigma_q = _sig("wdg_set_sigma_q", C.c_int32, _ctx, _dp)
+wdg_get_sigma_q = _sig("wdg_get_sigma_q", C.c_int32, _ctx, _dp)
+wdg_cubature_points = _sig("wdg_cubature_points", C.c_int32, _ctx, _dp)
+wdg_shell_energy = _sig("wdg_shell_energy", C.c_int32, _ctx, C.POINTER(wdg_shell), _dp, C.c_void_p)
+wdg_loss_gradient = _sig("wdg_loss_gradient", C.c_int32, _ctx, C.c_double, C.c_int32, C.POINTER(wdg_shell), C.c_int32,
+                         _dp, _dp, _dp, C.c_void_p)
 
 
 class WdgError(RuntimeError):
@@ -212,6 +223,24 @@ class Context:
         _check(wdg_memory_report(self.h, C.byref(m)), self.h)
         return {k: getattr(m, k) for k, _ in wdg_mem_t._fields_}
 
+    def cubature_points(self):
+        d = self.dims
+        out = np.zeros((d.K, d.Nq, 3))
+        _check(wdg_cubature_points(self.h, _ptr(out)), self.h)
+        return out
+
+    def get_sigma_q(self):
+        d = self.dims
+        out = np.zeros((d.K, d.Nq, 3))
+        _check(wdg_get_sigma_q(self.h, _ptr(out)), self.h)
+        return out
+
+    def set_sigma_q(self, sigma):
+        sigma = _f64(sigma)
+        d = self.dims
+        assert sigma.shape == (d.K, d.Nq, 3)
+        _check(wdg_set_sigma_q(self.h, _ptr(sigma)), self.h)
+
 
 class Simulation(Context):
     """A device context whose three state buffers are PyTorch CUDA (HIP) tensors."""
@@ -287,3 +316,62 @@ class Simulation(Context):
         e = C.c_double(0.0)
         _check(wdg_energy(self.h, C.byref(e), self._stream(stream)), self.h)
         return e.value
+
+    def shell_energy(self, shell, stream=None):
+        e = C.c_double(0.0)
+        sh = make_shell(shell)
+        _check(wdg_shell_energy(self.h, C.byref(sh), C.byref(e), self._stream(stream)), self.h)
+        return e.value
+
+    def loss_gradient(self, dt, nsteps, shell, checkpoint_interval=0, stream=None):
+        """(J, dJ/dsigma [K, Nq, 3], dJ/d(sigma_max xyz, L xyz, order) [7]); the state advances nsteps steps."""
+        d = self.dims
+        loss = C.c_double(0.0)
+        gs = np.zeros((d.K, d.Nq, 3))
+        gp = np.zeros(7)
+        sh = make_shell(shell)
+        _check(wdg_loss_gradient(self.h, float(dt), int(nsteps), C.byref(sh), int(checkpoint_interval), C.byref(loss),
+                                 _ptr(gs), _ptr(gp), self._stream(stream)), self.h)
+        return loss.value, gs, gp
+
+
+def make_shell(shell) -> wdg_shell:
+    sh = wdg_shell()
+    for i in range(3):
+        sh.outer_lo[i], sh.outer_hi[i] = float(shell["outer_lo"][i]), float(shell["outer_hi"][i])
+        sh.inner_lo[i], sh.inner_hi[i] = float(shell["inner_lo"][i]), float(shell["inner_hi"][i])
+    return sh
+
+
+def profile_sigma(xq, sigma_max, L, order, wall_lo, wall_hi):
+    """sigma at points xq [..., 3] (torch) of the profile sigma_max (d / L)^order per axis, where d is
+    the distance into the layer and the layer [wall - L, wall] ends at a fixed outer wall; differentiable
+    in sigma_max [3], L [3] and order (torch tensors)."""
+    lo = torch.as_tensor(wall_lo, dtype=xq.dtype) + L
+    hi = torch.as_tensor(wall_hi, dtype=xq.dtype) - L
+    d = torch.clamp(torch.maximum(xq - hi, lo - xq), min=0.0)
+    inside = d > 0
+    r = torch.where(inside, d / L, torch.ones_like(d))
+    return sigma_max * torch.where(inside, r ** order, torch.zeros_like(d))
+
+
+class ShellLoss(torch.autograd.Function):
+    """Loss sum_{n=1..nsteps} dt E_shell(q_n) as a function of sigma at the cubature points.
+
+    forward(sigma_q [K, Nq, 3] float64 tensor, sim, q0, t0, dt, nsteps, shell, checkpoint_interval) sets sigma,
+    the fields q0 and the time t0 on `sim`, runs the library's loss and adjoint sweep once and keeps
+    dJ/dsigma for backward."""
+
+    @staticmethod
+    def forward(ctx, sigma_q, sim, q0, t0, dt, nsteps, shell, checkpoint_interval=0):
+        sim.set_sigma_q(sigma_q.detach().cpu().numpy())
+        sim.set_fields(q0)
+        sim.set_time(t0)
+        loss, gs, _ = sim.loss_gradient(dt, nsteps, shell, checkpoint_interval)
+        ctx.save_for_backward(torch.from_numpy(gs).to(sigma_q.device, sigma_q.dtype))
+        return torch.tensor(loss, dtype=sigma_q.dtype, device=sigma_q.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return (gout * g, None, None, None, None, None, None, None)

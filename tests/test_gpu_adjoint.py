@@ -1,0 +1,224 @@
+"""GPU parity of the loss-gradient path (through the C ABI) against the FP64
+oracle's discrete adjoint (oracle.adjoint), plus finite-difference checks at
+the full 48,000-tetrahedron size where the oracle is too slow.
+
+Tolerances: FP64 loss 1e-12 relative, gradients 1e-10 relative to their
+largest entry (the per-tile sums over the six components are accumulated with
+LDS atomics, so their order, and the last bits, vary between runs); FP32
+1e-5 (loss) and 2e-4 (gradient) against the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_02551_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHELL_C1 = {"outer_lo": [-0.5] * 3, "outer_hi": [0.5] * 3, "inner_lo": [-0.3] * 3, "inner_hi": [0.3] * 3}
+# the shell 0.1 inside the PML interface of the 48,000-tetrahedron workload
+SHELL_C5 = {"outer_lo": [-1.0] * 3, "outer_hi": [1.0] * 3, "inner_lo": [-0.9] * 3, "inner_hi": [0.9] * 3}
+
+
+@pytest.fixture(scope="module")
+def wdg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2006_02551_amd import wdg as w
+    return w
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(wdg, cfg, precision=0, seed=0):
+    from oracle.run import Simulation as OSim
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+    osim = OSim(cfg, vx, ev, *rule)
+    rng = np.random.default_rng(seed)
+    q0 = inputs.gaussian_fields(cfg, osim.mesh.x)
+    q0[:, 0:6] += 0.05 * rng.standard_normal(q0[:, 0:6].shape)
+    q0[osim.op.is_pml, 6:] = 0.05 * rng.standard_normal((int(osim.op.is_pml.sum()), 6, osim.ref.Np))
+    if cfg.get("source"):
+        sim.set_dipole(cfg["source"])
+    sim.set_fields(q0)
+    osim.set_state(q0)
+    return sim, osim, q0
+
+
+def _oracle_grad(osim, q0, nsteps, shell):
+    from oracle import adjoint as A
+    J, g, _ = A.loss_and_gradient(osim.op, q0, 0.0, osim.dt, nsteps, shell)
+    full = np.zeros((osim.mesh.K, osim.ref.Nq, 3))
+    full[osim.op.pml_elems] = g
+    return J, full, A.profile_gradient(osim.op, _pml(osim.cfg), g)
+
+
+def _pml(cfg):
+    p = dict(cfg["pml"])
+    p["order"] = float(p["order"])
+    return p
+
+
+def test_shell_energy_matches_oracle(wdg):
+    from oracle import adjoint as A
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
+    _say("shell energy")
+    for precision, tol in ((0, 1e-13), (1, 1e-6)):
+        sim, osim, q0 = _pair(wdg, cfg, precision)
+        chi = A.shell_weights(osim.op, SHELL_C1)
+        ref = A.shell_energy(osim.op, chi, q0)
+        got = sim.shell_energy(SHELL_C1)
+        assert ref > 0 and abs(got - ref) <= tol * ref, (precision, got, ref)
+
+
+@pytest.mark.parametrize("name,over,nsteps", [
+    ("c1", {"mesh.perturb": 0.1, "init.width": 0.35}, 12),            # N = 2, quadratic profile
+    ("c2", {"mesh.n": 5, "init": {"component": 2, "center": [0.0] * 3, "width": 0.5}}, 8),  # N = 3, cubic, dipole
+], ids=["c1", "c2n5"])
+def test_loss_and_gradient_match_oracle_fp64(wdg, name, over, nsteps):
+    cfg = inputs.config(name, **over)
+    shell = SHELL_C1 if name == "c1" else SHELL_C5
+    _say(f"loss gradient fp64 {name} {over} {nsteps} steps")
+    sim, osim, q0 = _pair(wdg, cfg, 0)
+    J, g, gp = sim.loss_gradient(osim.dt, nsteps, shell)
+    Jr, gr, gpr = _oracle_grad(osim, q0, nsteps, shell)
+    assert Jr > 0 and abs(J - Jr) <= 1e-12 * Jr, (J, Jr)
+    scale = np.max(np.abs(gr))
+    assert scale > 0
+    assert np.max(np.abs(g - gr)) <= 1e-10 * scale, np.max(np.abs(g - gr)) / scale
+    assert np.max(np.abs(gp - gpr)) <= 1e-10 * np.max(np.abs(gpr)), (gp, gpr)
+    # the state advanced exactly as plain stepping does
+    sim2, _, _ = _pair(wdg, cfg, 0)
+    sim2.step(osim.dt, nsteps)
+    assert np.array_equal(sim.get_fields(), sim2.get_fields())
+
+
+def test_loss_and_gradient_fp32_against_fp64_oracle(wdg):
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
+    _say("loss gradient fp32")
+    sim, osim, q0 = _pair(wdg, cfg, 1)
+    J, g, gp = sim.loss_gradient(osim.dt, 12, SHELL_C1)
+    Jr, gr, gpr = _oracle_grad(osim, q0, 12, SHELL_C1)
+    err_j, err_g = abs(J - Jr) / Jr, np.max(np.abs(g - gr)) / np.max(np.abs(gr))
+    _say(f"  fp32 loss error {err_j:.2e}, gradient error {err_g:.2e}")
+    assert err_j <= 1e-5 and err_g <= 2e-4
+
+
+def test_checkpoint_interval_and_empty_shell(wdg):
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
+    _say("checkpoint intervals")
+    res = []
+    for interval in (1, 3, 0, 20):
+        sim, osim, q0 = _pair(wdg, cfg, 0)
+        res.append(sim.loss_gradient(osim.dt, 10, SHELL_C1, interval))
+    for J, g, gp in res[1:]:
+        assert J == res[0][0]  # the forward sweep is deterministic
+        assert np.max(np.abs(g - res[0][1])) <= 1e-13 * np.max(np.abs(res[0][1]))
+    sim, osim, q0 = _pair(wdg, cfg, 0)
+    empty = {"outer_lo": [5.0] * 3, "outer_hi": [6.0] * 3, "inner_lo": [5.5] * 3, "inner_hi": [5.6] * 3}
+    J, g, gp = sim.loss_gradient(osim.dt, 4, empty)
+    assert J == 0.0 and not np.any(g) and not np.any(gp)
+    assert sim.shell_energy(empty) == 0.0
+
+
+def test_c5_full_size_gradient_matches_finite_differences(wdg):
+    # The differentiation workload: the 48,000-tet N = 3 mesh, 500 steps, a
+    # pulse that reaches the layer, the loss in the shell 0.1 inside the PML
+    # interface.  The oracle would take hours, so the adjoint gradient is
+    # checked against central differences (relative step 1e-6) of the GPU loss.
+    cfg = inputs.config("c5")
+    shell = cfg["shell"]
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    nsteps = cfg["steps"]
+    _say("c5 full size: adjoint vs central differences")
+    sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], 0)
+    q0 = inputs.gaussian_fields(cfg, sim.node_coords())
+    dt = cfg["cfl"] * sim.dims.dt_unit
+    sig0 = sim.get_sigma_q()
+    sim.set_fields(q0)
+    sim.set_time(0.0)
+    J, g, gp = sim.loss_gradient(dt, nsteps, shell)
+    _say(f"  J = {J:.6e}, dJ/dsigma_max = {gp[:3]}, dJ/dL = {gp[3:6]}, dJ/dp = {gp[6]:.4e}")
+    assert J > 0 and np.all(np.isfinite(g)) and np.max(np.abs(gp[:3])) > 0
+
+    def loss_with(sig):
+        sim.set_sigma_q(sig)
+        sim.set_fields(q0)
+        sim.set_time(0.0)
+        return sim.loss_gradient(dt, nsteps, shell)[0]
+
+    rounding = 100 * np.finfo(float).eps * J
+    smax = np.asarray(cfg["pml"]["sigma_max"], float)
+    for a in range(3):
+        h = 1e-6 * smax[a]
+        sp, sm = sig0.copy(), sig0.copy()
+        sp[..., a] *= 1.0 + h / smax[a]   # sigma_a is proportional to sigma_max_a
+        sm[..., a] *= 1.0 - h / smax[a]
+        fd = (loss_with(sp) - loss_with(sm)) / (2 * h)
+        _say(f"  axis {a}: adjoint {gp[a]:.10e}  central difference {fd:.10e}  rounding bound {rounding / h:.1e}")
+        assert abs(fd - gp[a]) <= 1e-5 * abs(fd) + rounding / h
+    # all three sigma_max scaled together: d/de J((1 + e) sigma) = sum_a sigma_max_a dJ/dsigma_max_a,
+    # large enough for the rounding bound to be a small fraction of it
+    eps = 1e-6
+    fd = (loss_with(sig0 * (1 + eps)) - loss_with(sig0 * (1 - eps))) / (2 * eps)
+    adj = float(np.dot(smax, gp[:3]))
+    _say(f"  uniform scaling: adjoint {adj:.10e}  central difference {fd:.10e}  rounding bound {rounding / eps:.1e}")
+    assert rounding / eps < 0.1 * abs(fd)  # the check is not vacuous
+    assert abs(fd - adj) <= 1e-5 * abs(fd) + rounding / eps
+    # the profile order, sigma recomputed at the cubature points (interface and wall unchanged)
+    from oracle.pml import sigma_kappa
+    xq = sim.cubature_points()
+    p0 = float(cfg["pml"]["order"])
+    h = 1e-6 * p0
+    vals = []
+    for sgn in (1.0, -1.0):
+        pml = dict(cfg["pml"], order=p0 + sgn * h)
+        sig = sigma_kappa(xq, pml)[0]
+        assert not np.any((sig != 0) != (sig0 != 0))
+        vals.append(loss_with(sig))
+    fd = (vals[0] - vals[1]) / (2 * h)
+    _say(f"  order: adjoint {gp[6]:.10e}  central difference {fd:.10e}  rounding bound {rounding / h:.1e}")
+    assert rounding / h < 0.1 * abs(fd)
+    assert abs(fd - gp[6]) <= 1e-5 * abs(fd) + rounding / h
+    # a few single cubature nodes with the largest sensitivity
+    idx = np.argsort(np.abs(g).ravel())[::-1][:2]
+    for i in idx:
+        k, q, a = np.unravel_index(i, g.shape)
+        h = 1e-6 * max(1.0, abs(sig0[k, q, a]))
+        sp, sm = sig0.copy(), sig0.copy()
+        sp[k, q, a] += h
+        sm[k, q, a] -= h
+        fd = (loss_with(sp) - loss_with(sm)) / (2 * h)
+        _say(f"  node {(k, q, a)}: adjoint {g[k, q, a]:.10e}  central difference {fd:.10e}")
+        assert abs(fd - g[k, q, a]) <= 1e-5 * abs(fd) + rounding / h
+    sim.set_sigma_q(sig0)
+
+
+def test_autograd_function_chain_rule(wdg):
+    import torch
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
+    _say("torch.autograd.Function")
+    sim, osim, q0 = _pair(wdg, cfg, 0)
+    pml = cfg["pml"]
+    xq = torch.from_numpy(sim.cubature_points())
+    smax = torch.tensor(pml["sigma_max"], dtype=torch.float64, requires_grad=True)
+    L = torch.tensor(pml["L"], dtype=torch.float64, requires_grad=True)
+    order = torch.tensor(float(pml["order"]), dtype=torch.float64, requires_grad=True)
+    wall_lo = np.asarray(pml["lo"], float) - np.asarray(pml["L"], float)
+    wall_hi = np.asarray(pml["hi"], float) + np.asarray(pml["L"], float)
+    sig = wdg.profile_sigma(xq, smax, L, order, wall_lo, wall_hi)
+    assert np.max(np.abs(sig.detach().numpy() - sim.get_sigma_q())) <= 1e-12 * pml["sigma_max"][0]
+    loss = wdg.ShellLoss.apply(sig, sim, q0, 0.0, osim.dt, 10, SHELL_C1, 0)
+    loss.backward()
+    got = np.concatenate([smax.grad.numpy(), L.grad.numpy(), [order.grad.item()]])
+    sim.set_fields(q0)
+    sim.set_time(0.0)
+    _, _, gp = sim.loss_gradient(osim.dt, 10, SHELL_C1)
+    assert np.max(np.abs(got - gp)) <= 1e-10 * np.max(np.abs(gp)), (got, gp)

@@ -121,3 +121,39 @@ def test_negative_orientation_is_swapped_like_the_oracle():
     osim = OSim(cfg, vx, ev2, *rule)
     assert np.allclose(ctx.node_coords(), osim.mesh.x, atol=1e-14)
     assert np.allclose(ctx.element_info()["J"], osim.mesh.J)
+
+
+def test_sigma_readout_override_and_cubature_points():
+    from oracle.run import Simulation as OSim
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1})
+    ctx, vx, ev, rule = _ctx(cfg)
+    osim = OSim(cfg, vx, ev, *rule)
+    assert np.allclose(ctx.cubature_points(), osim.op.xq, atol=1e-14)
+    sig = ctx.get_sigma_q()
+    assert np.max(np.abs(sig - osim.op.sigma)) <= 1e-13 * np.max(sig)
+    # a valid override round-trips; non-zero sigma outside the PML is refused
+    new = sig * 1.5
+    ctx.set_sigma_q(new)
+    assert np.array_equal(ctx.get_sigma_q(), new)
+    bad = new.copy()
+    k_int = int(np.nonzero(~osim.op.is_pml)[0][0])
+    bad[k_int, 0, 0] = 1.0
+    with pytest.raises(wdg.WdgError) as e:
+        ctx.set_sigma_q(bad)
+    assert e.value.code == wdg.WDG_EINVAL
+    bad = new.copy()
+    bad[int(osim.op.pml_elems[0]), 0, 1] = np.nan
+    with pytest.raises(wdg.WdgError):
+        ctx.set_sigma_q(bad)
+    assert np.array_equal(ctx.get_sigma_q(), new)
+
+
+def test_loss_gradient_needs_device_state():
+    cfg = inputs.config("c1")
+    ctx, *_ = _ctx(cfg)
+    sh = wdg.make_shell({"outer_lo": [-0.5] * 3, "outer_hi": [0.5] * 3, "inner_lo": [-0.4] * 3, "inner_hi": [0.4] * 3})
+    import ctypes as C
+    loss = C.c_double(0.0)
+    assert wdg.wdg_loss_gradient(ctx.h, 0.01, 5, C.byref(sh), 0, C.byref(loss), None, None, None) == wdg.WDG_ESTATE
+    assert wdg.wdg_loss_gradient(ctx.h, 0.01, -1, C.byref(sh), 0, C.byref(loss), None, None, None) == wdg.WDG_EINVAL
+    assert wdg.wdg_shell_energy(ctx.h, C.byref(sh), C.byref(loss), None) == wdg.WDG_ESTATE
