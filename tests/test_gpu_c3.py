@@ -1,0 +1,89 @@
+"""The precision form at full size: 40^3 x 6 = 384,000 perturbed tetrahedra,
+N = 4, degree-8 cubature (51 points), quadratic profile sigma_max = 40, dipole.
+
+* the right-hand side of sampled elements against the FP64 oracle (FP64: the
+  scalar-operand kernel, since the FP64 matrix-core kernel at N = 4 needs more
+  LDS than a compute unit has; FP32: the matrix-core kernel);
+* FP32 stepping against FP64 stepping on the GPU over the recipe's 2,000
+  steps, relative L2 error of E, H reported at steps 100, 1,000 and 2,000
+  (the oracle itself would need hours per hundred steps at this size; the FP64
+  path is the one checked against it above and in test_gpu_parity.py).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_02551_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wdg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2006_02551_amd import wdg as w
+    return w
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    cfg = inputs.config("c3")
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    return cfg, vx, ev, rule
+
+
+def test_c3_full_size_rhs_sampled(wdg, c3):
+    from oracle.run import Simulation as OSim
+    cfg, vx, ev, rule = c3
+    _say("c3 oracle setup (384,000 elements)")
+    osim = OSim(cfg, vx, ev, *rule)
+    rng = np.random.default_rng(13)
+    q = rng.standard_normal((osim.mesh.K, 12, osim.ref.Np))
+    q[~osim.op.is_pml, 6:] = 0.0
+    el = np.unique(np.concatenate([rng.choice(osim.mesh.K, 300, replace=False), osim.op.pml_elems[:40],
+                                   np.nonzero(~osim.op.is_pml)[0][:40], [0, osim.mesh.K - 1]]))
+    t = 0.83
+    ref = osim.op.rhs(q, t, el=el)
+    scale = np.max(np.abs(ref))
+    for precision, tol in ((0, 1e-12), (1, 2e-5)):
+        _say(f"c3 sampled rhs precision {precision}")
+        sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+        sim.set_dipole(cfg["source"])
+        sim.set_fields(q)
+        sim.rhs(t)
+        got = sim.get_residual()
+        err = np.max(np.abs(got[el] - ref)) / scale
+        _say(f"  kernel {sim.dims.kernel}, max error {err:.2e}")
+        assert err <= tol
+        del sim
+
+
+def test_c3_fp32_against_fp64_over_2000_steps(wdg, c3):
+    cfg, vx, ev, rule = c3
+    sims = {}
+    for precision in (0, 1):
+        sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+        sim.set_dipole(cfg["source"])
+        sim.set_fields(np.zeros((sim.dims.K, 12, sim.dims.Np)))
+        sims[precision] = sim
+    dt = cfg["cfl"] * sims[0].dims.dt_unit
+    done = 0
+    errors = {}
+    for target in (100, 1000, 2000):
+        for sim in sims.values():
+            sim.step(dt, target - done)
+        done = target
+        a, b = sims[0].get_fields()[:, 0:6], sims[1].get_fields()[:, 0:6]
+        errors[target] = float(np.linalg.norm(b - a) / np.linalg.norm(a))
+        _say(f"c3 step {target}: FP32 relative L2 error against FP64 {errors[target]:.3e} "
+             f"(field norm {np.linalg.norm(a):.3e})")
+        assert np.isfinite(errors[target])
+    assert errors[2000] <= 1e-5
