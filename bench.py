@@ -12,7 +12,11 @@ inverse mass and the Runge-Kutta update) plus the probe readout.  Fields live
 in HBM before the timed region starts.  The metric is
 K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
 
-Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--copy-calibration MIB]
+Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`) and the
+batching form's throughput (`batch`: 32 independent simulations in one context).
+
+Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--stepping-only]
+                       [--copy-calibration MIB]
 """
 from __future__ import annotations
 
@@ -30,9 +34,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 # (scale factors from a 1 GiB device copy), taken on the kernel source with
 # this sha256; reported only while the source is unchanged.
 MEASURED_TRAFFIC = {
-    "source_sha256": "0ffa1410f5e53991d4ee5adf5c0e071d75be0671101c7be8246dcb74da1d8a8a",
-    "stage_mfma_kernel<double,N=3,Nq=24>": (119995.8 * 2.0 + 160560.0) * 1024,
-    "stage_mfma_kernel<float,N=3,Nq=24>": (64164.7 * 2.0 + 97069.9) * 1024,
+    "source_sha256": "9c4b78953cec066d278ce000c97be1e6a6dc24481931188c2f23cdfd7ae6657a",
+    "stage_mfma_kernel<double,N=3,Nq=24>": (119944.8 * 2.0 + 160560.0) * 1024,
+    "stage_mfma_kernel<float,N=3,Nq=24>": (64331.9 * 2.0 + 94816.3) * 1024,
 }
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)
@@ -157,6 +161,61 @@ def run_adjoint(precision):
             "dJ_dsigma_max": list(gp[:3]), "dJ_dL": list(gp[3:6]), "dJ_dorder": gp[6]}
 
 
+def run_batch(steps, warmup, seq_steps=50):
+    """The batching form: 32 independent simulations (8^3 x 6 .. 24^3 x 6 tets, 1,282,008 in all, N=3, each
+    with its own sigma profile and time step) stepped in one context in FP32 with captured two-step graphs,
+    against the same simulations stepped one after another, each in a context of its own."""
+    import torch
+
+    from paper_2006_02551_amd import inputs, wdg
+    from paper_2006_02551_amd.batch import Batch
+
+    cfg = inputs.config("c4")
+    b = Batch(cfg, wdg.WDG_FP32)
+    d = b.sim.dims
+    tune = b.sim.autotune(reps=5, stream=b.stream)
+    chosen = {"kernel": "mfma" if b.sim.dims.kernel == wdg.WDG_KERNEL_MFMA else "scalar", "tiles": b.sim.dims.tiles}
+    b.set_fields(b.initial_fields())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    b.step(warmup, graph=True)
+    torch.cuda.synchronize()
+    ev[0].record(b.stream)
+    b.step(steps, graph=True)
+    ev[1].record(b.stream)
+    b.step(steps, graph=False)
+    ev[2].record(b.stream)
+    torch.cuda.synchronize()
+    ms_graph, ms_eager = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    q = b.sim.get_fields()
+    assert all(bool(abs(x) < 1e30) for x in (q.max(), q.min()))
+    dofs = d.K * d.Np
+    del b.sim
+    # the same simulations one after another
+    ms_seq = 0.0
+    stream = torch.cuda.current_stream()
+    for i, (vx, ev_i) in enumerate(b.meshes):
+        sim = wdg.Simulation(vx, ev_i, cfg["N"], b.rule, b.standalone_pml(i), cfg["alpha"], wdg.WDG_FP32)
+        sim.set_fields(inputs.gaussian_fields(cfg, sim.node_coords()))
+        sim.step(float(b.dt[i]), 2, stream)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        sim.step(float(b.dt[i]), seq_steps, stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        ms_seq += ev[0].elapsed_time(ev[3]) / seq_steps
+        del sim
+    return {"value": dofs * steps / (ms_graph / 1e3), "ms_per_step": ms_graph / steps, "dtype": "f32",
+            "eager_value": dofs * steps / (ms_eager / 1e3),
+            "sequential_value": dofs / (ms_seq / 1e3), "sequential_ms_per_step": ms_seq,
+            "speedup_vs_sequential": ms_seq / (ms_graph / steps),
+            "autotune_us_per_stage": tune, "chosen": chosen, "K": d.K, "K_pml": d.K_pml, "nsim": len(b.meshes),
+            "steps": steps,
+            "workload": "c4: 32 simulations, meshes 8^3x6 .. 24^3x6 perturbed tets (1,282,008 in all), N=3, "
+                        "sigma_max in [10, 50] and order in {2, 3, 4} per simulation, per-simulation dt, "
+                        "Gaussian Ez pulse, FP32, one launch per stage for the whole batch, two-step HIP graphs; "
+                        "sequential = each simulation in its own context, eager steps, one after another"}
+
+
 def cpu_baseline(cfg, steps=3):
     """The FP64 oracle on the host cores for a bounded sample (three LSERK4 steps, about 15 s)."""
     import numpy as np
@@ -184,6 +243,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stepping-only", action="store_true",
+                    help="run the c2 stepping legs only (no adjoint or batch legs), e.g. under a profiler")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (a known-size reference for "
                          "hardware traffic counters)")
@@ -214,10 +275,17 @@ def main():
           file=sys.stderr, flush=True)
     r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup)
     print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    print("bench: adjoint (loss gradient) against plain stepping, 500 steps, FP64 and FP32", file=sys.stderr, flush=True)
-    adj64 = run_adjoint(wdg.WDG_FP64)
-    adj32 = run_adjoint(wdg.WDG_FP32)
-    print(f"bench: adjoint/forward {adj64['ratio']:.2f} (FP64), {adj32['ratio']:.2f} (FP32)", file=sys.stderr, flush=True)
+    adj64 = adj32 = batch = None
+    if not args.stepping_only:
+        print("bench: adjoint (loss gradient) against plain stepping, 500 steps, FP64 and FP32", file=sys.stderr,
+              flush=True)
+        adj64 = run_adjoint(wdg.WDG_FP64)
+        adj32 = run_adjoint(wdg.WDG_FP32)
+        print(f"bench: adjoint/forward {adj64['ratio']:.2f} (FP64), {adj32['ratio']:.2f} (FP32); batch next",
+              file=sys.stderr, flush=True)
+        batch = run_batch(max(args.steps // 5, 20), 4)
+        print(f"bench: batch {batch['value']:.3e} DOF/s ({batch['speedup_vs_sequential']:.2f}x sequential)",
+              file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on three steps", file=sys.stderr, flush=True)
@@ -252,13 +320,14 @@ def main():
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "achieved_tflops": r64["achieved_tflops"],
                      "flop_frac": r64["achieved_tflops"] / FP64_PEAK_TFLOPS},
-        "adjoint_forward_ratio": {
+        "adjoint_forward_ratio": None if adj64 is None else {
             "value": adj64["ratio"], "fp32": adj32["ratio"],
             "workload": "c5: the 48,000-tet N=3 mesh, Gaussian Ez pulse, 500 LSERK4 steps, loss = time-integrated "
                         "energy in the shell 0.1 inside the PML interface, gradient by the discrete adjoint with "
                         "sqrt(T) checkpoints (wall time of wdg_loss_gradient / 500 plain steps)",
             "fp64": {k: v for k, v in adj64.items() if k != "ratio"},
             "fp32_detail": {k: v for k, v in adj32.items() if k != "ratio"}},
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

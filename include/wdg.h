@@ -100,6 +100,7 @@ typedef struct wdg_dims_t {
     double time;         /* current simulation time */
     int64_t steps;       /* steps taken since creation / last set_fields */
     int32_t kernel;      /* active stage-kernel variant (WDG_KERNEL_*) */
+    int32_t tiles;       /* 16-element tiles per workgroup of the matrix-core kernel (1 or 2) */
 } wdg_dims_t;
 
 /* Gaussian-modulated dipole current, added to dE/dt as -J:
@@ -188,6 +189,41 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
  * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64,
  * FP32 only). */
 int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
+
+/* Tiles of 16 elements per workgroup of the matrix-core kernel: 1 or 2 (the
+ * default).  Results do not depend on it. */
+int32_t wdg_set_tiles(wdg_ctx* ctx, int32_t tiles);
+
+/* Times the available stage kernels (scalar-operand; matrix-core with 1 and 2
+ * tiles per workgroup) over `reps` stage launches each on the current state
+ * (best of three) and selects the fastest.  times_us double [3] (may be NULL)
+ * receives the microseconds per launch, -1 where unavailable.  The fields are
+ * unchanged; the Runge-Kutta residual is overwritten (a step starts by
+ * resetting it).  Synchronises hip_stream. */
+int32_t wdg_autotune(wdg_ctx* ctx, int32_t reps, double* times_us, void* hip_stream);
+
+/* Advances nsteps steps like wdg_step by replaying a captured HIP graph of two
+ * steps (ten stage launches), re-captured when dt, the kernel choice or the
+ * bound buffers change; an odd last step is launched directly.  Needs a
+ * non-NULL stream, no dipole source and no probes (WDG_EINVAL): the source
+ * amplitude and the probe row change every step. */
+int32_t wdg_step_graph(wdg_ctx* ctx, double dt, int32_t nsteps, void* hip_stream);
+
+/* Per-element factor on the time step, double [K] in user element order (NULL
+ * removes it): element k advances with dt * scale[k], so independent
+ * simulations held in one context (disjoint meshes) each keep their own stable
+ * step.  Values must be positive and finite.  The context time advances by dt;
+ * the source amplitude follows it. */
+int32_t wdg_set_dt_scale(wdg_ctx* ctx, const double* scale);
+
+/* Per-group PML profiles: element k of group group[k] (int32 [K], 0..ngroups-1)
+ * gets sigma_u = sigma_max[g][u] (d_u / L_u)^order[g] at its cubature points
+ * (interface box and thickness as given at creation; elements outside the PML
+ * stay zero), so independent simulations in one context keep their own
+ * conductivity.  Needs kappa = 1.  sigma_max double [ngroups][3], order
+ * double [ngroups]. */
+int32_t wdg_set_sigma_profile(wdg_ctx* ctx, const int32_t* group, int32_t ngroups, const double* sigma_max,
+                              const double* order);
 
 /* Advances nsteps LSERK4 steps of size dt, enqueued on hip_stream (a
  * hipStream_t; NULL for the default stream), without synchronising.

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdg.so")
 ARCH = "gfx950"
 
-SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_adjoint.hip"]
+SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "batch.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_adjoint.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(HERE, '..', 'include')}"]
 # Packed FP32 instructions are disabled for all device code.

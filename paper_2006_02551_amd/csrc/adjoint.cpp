@@ -195,6 +195,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
     if (int e = check_state(c)) return e;
     const Setup& S = c->S;
     if (S.has_kappa) return fail(c, WDG_EINVAL, "the adjoint needs kappa = 1");
+    if (c->has_dt_scale) return fail(c, WDG_EINVAL, "the adjoint needs one time step for all elements");
     if (!adjoint_supported(S.ref.N, S.ref.Nq, c->precision))
         return fail(c, WDG_EINVAL, "no adjoint kernel for this order, rule size and precision");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

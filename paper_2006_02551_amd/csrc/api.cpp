@@ -223,6 +223,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.src_slot = static_cast<const int*>(c->src_slot.p);
     p.src = c->src.p;
     p.frags = c->frags.p;
+    p.dt_scale = c->has_dt_scale ? static_cast<const double*>(c->dt_scale.p) : nullptr;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;
@@ -237,7 +238,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
         const double tt = t - d.t0;
         p.src_g = d.amplitude * std::sin(2.0 * M_PI * d.f0 * tt) * std::exp(-(tt / d.tau) * (tt / d.tau));
     }
-    const int e = c->kernel == WDG_KERNEL_MFMA ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, p, stream)
+    const int e = c->kernel == WDG_KERNEL_MFMA ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, c->tpw, p, stream)
                                                : launch_stage(c->precision, S.ref.N, S.has_kappa, p, stream);
     if (e != 0) return fail(c, WDG_EHIP, std::string("stage launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
     return WDG_OK;
@@ -331,6 +332,7 @@ int32_t wdg_get_dims(const wdg_ctx* c, wdg_dims_t* o) {
     o->time = c->t;
     o->steps = c->steps;
     o->kernel = c->kernel;
+    o->tiles = c->tpw;
     return WDG_OK;
 }
 

@@ -1,0 +1,214 @@
+// Many independent simulations in one launch, captured stepping and the
+// stage-kernel autotuner (C ABI part).
+//
+// Independent simulations share a context as one mesh with disjoint vertex
+// sets (no face is shared, so no flux couples them).  Each keeps its own PML
+// profile (wdg_set_sigma_profile) and its own stable time step (a per-element
+// factor on dt, wdg_set_dt_scale); every element's arithmetic is independent
+// of the other columns of its tile, so a simulation in a batch reproduces its
+// standalone run bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "context.hpp"
+
+using namespace wdg;
+
+namespace {
+
+int launch_steps(wdg_ctx* c, double dt, int nsteps, hipStream_t s) {
+    for (int n = 0; n < nsteps; ++n) {
+        for (int i = 0; i < 5; ++i) {
+            const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[i], kRkB[i], dt, c->t + kRkC[i] * dt,
+                                           i > 0, s);
+            if (rc != WDG_OK) return rc;
+            c->cur = 1 - c->cur;
+        }
+        c->t += dt;
+        c->steps += 1;
+    }
+    return WDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
+    if (!c) return WDG_EINVAL;
+    if (tiles != 1 && tiles != 2) return fail(c, WDG_EINVAL, "tiles per workgroup must be 1 or 2");
+    c->tpw = tiles;
+    return WDG_OK;
+}
+
+int32_t wdg_set_dt_scale(wdg_ctx* c, const double* scale) {
+    if (!c) return WDG_EINVAL;
+    if (c->host_only) return fail(c, WDG_ESTATE, "host-only context");
+    return guarded(c, [&]() -> int {
+        const Setup& S = c->S;
+        if (!scale) {
+            c->has_dt_scale = false;
+            c->dt_scale.alloc(0);
+            return WDG_OK;
+        }
+        std::vector<double> d(static_cast<size_t>(S.nblk) * S.B, 1.0);
+        for (int k = 0; k < S.K; ++k) {
+            if (!(scale[k] > 0.0) || !std::isfinite(scale[k])) return fail(c, WDG_EINVAL, "dt scale must be positive and finite");
+            d[S.perm[k]] = scale[k];
+        }
+        c->dt_scale.upload(d.data(), d.size() * sizeof(double));
+        c->has_dt_scale = true;
+        return WDG_OK;
+    });
+}
+
+int32_t wdg_set_sigma_profile(wdg_ctx* c, const int32_t* group, int32_t ngroups, const double* sigma_max, const double* order) {
+    if (!c || !group || ngroups <= 0 || !sigma_max || !order) return WDG_EINVAL;
+    return guarded(c, [&]() -> int {
+        Setup& S = c->S;
+        if (S.has_kappa) return fail(c, WDG_EINVAL, "per-group profiles need kappa = 1");
+        for (int g = 0; g < ngroups; ++g) {
+            if (!(order[g] >= 0.0)) return fail(c, WDG_EINVAL, "profile order must be >= 0");
+            for (int d = 0; d < 3; ++d)
+                if (!(sigma_max[3 * g + d] >= 0.0)) return fail(c, WDG_EINVAL, "sigma_max must be >= 0");
+        }
+        const int Nq = S.ref.Nq;
+        std::vector<double> sig(static_cast<size_t>(S.K) * Nq * 3, 0.0);
+        for (int k = 0; k < S.K; ++k) {
+            const int g = group[k];
+            if (g < 0 || g >= ngroups) return fail(c, WDG_EINVAL, "group index out of range");
+            if (!S.is_pml[k]) continue;
+            for (int q = 0; q < Nq; ++q)
+                for (int d = 0; d < 3; ++d) {
+                    const size_t i = (static_cast<size_t>(k) * Nq + q) * 3 + d;
+                    sig[i] = sigma_max[3 * g + d] *
+                             profile_ratio(S.xq[i], S.pml.lo[d], S.pml.hi[d], S.pml.L[d], order[g]);
+                }
+        }
+        S.sigma.swap(sig);
+        if (!c->host_only) upload_coefficients(c);
+        return WDG_OK;
+    });
+}
+
+int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) {
+    if (!c || nsteps < 0 || !std::isfinite(dt)) return WDG_EINVAL;
+    if (int e = check_state(c)) return e;
+    if (!hip_stream) return fail(c, WDG_EINVAL, "graph stepping needs a non-null stream");
+    if (c->has_src) return fail(c, WDG_EINVAL, "graph stepping needs no source (its amplitude changes every stage)");
+    if (c->nprobe > 0) return fail(c, WDG_EINVAL, "graph stepping needs no probes");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return guarded(c, [&]() -> int {
+        const int pairs = nsteps / 2;
+        if (pairs > 0) {
+            const bool same = c->graph && c->graph_dt == dt && c->graph_cur == c->cur && c->graph_kernel == c->kernel &&
+                              c->graph_tpw == c->tpw && c->graph_bufs[0] == c->q[0] && c->graph_bufs[1] == c->q[1] &&
+                              c->graph_bufs[2] == c->res;
+            if (!same) {
+                if (c->graph) {
+                    hip_check(hipGraphExecDestroy(c->graph), "graph destroy");
+                    c->graph = nullptr;
+                }
+                // Capture two steps (ten stage launches): the buffer roles are
+                // back where they started, so one graph serves every pair.
+                const int cur0 = c->cur;
+                const double t0 = c->t;
+                const int64_t s0 = c->steps;
+                hipGraph_t g = nullptr;
+                hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+                const int rc = launch_steps(c, dt, 2, s);
+                const hipError_t ec = hipStreamEndCapture(s, &g);
+                c->cur = cur0;
+                c->t = t0;
+                c->steps = s0;
+                if (rc != WDG_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                hip_check(ec, "end capture");
+                hipGraphExec_t ex = nullptr;
+                const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                hip_check(ei, "graph instantiate");
+                c->graph = ex;
+                c->graph_dt = dt;
+                c->graph_cur = c->cur;
+                c->graph_kernel = c->kernel;
+                c->graph_tpw = c->tpw;
+                c->graph_bufs[0] = c->q[0];
+                c->graph_bufs[1] = c->q[1];
+                c->graph_bufs[2] = c->res;
+            }
+            for (int i = 0; i < pairs; ++i) hip_check(hipGraphLaunch(c->graph, s), "graph launch");
+            // the clock advances as eager stepping advances it, one dt at a time
+            for (int i = 0; i < 2 * pairs; ++i) c->t += dt;
+            c->steps += 2 * pairs;
+        }
+        if (nsteps % 2) return launch_steps(c, dt, 1, s);
+        return WDG_OK;
+    });
+}
+
+int32_t wdg_autotune(wdg_ctx* c, int32_t reps, double* times_us, void* hip_stream) {
+    if (!c || reps < 1) return WDG_EINVAL;
+    if (int e = check_state(c)) return e;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return guarded(c, [&]() -> int {
+        struct Cand {
+            int kernel, tpw;
+        };
+        const Cand cands[3] = {{WDG_KERNEL_SCALAR, 2}, {WDG_KERNEL_MFMA, 1}, {WDG_KERNEL_MFMA, 2}};
+        double best = std::numeric_limits<double>::infinity();
+        int best_i = -1;
+        const int kernel0 = c->kernel, tpw0 = c->tpw;
+        hipEvent_t a = nullptr, b = nullptr;
+        hip_check(hipEventCreate(&a), "event");
+        hip_check(hipEventCreate(&b), "event");
+        int rc = WDG_OK;
+        for (int i = 0; i < 3 && rc == WDG_OK; ++i) {
+            double t_us = -1.0;
+            if (cands[i].kernel != WDG_KERNEL_MFMA || c->mfma_ok) {
+                c->kernel = cands[i].kernel;
+                c->tpw = cands[i].tpw;
+                // a stage as in the middle of a step: reads and writes the residual,
+                // writes the spare field buffer; the current fields are untouched
+                auto stage = [&]() {
+                    return launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[1], kRkB[1], 1e-30, c->t, true, s);
+                };
+                rc = stage();  // warm-up
+                float best_ms = std::numeric_limits<float>::infinity();
+                for (int trial = 0; trial < 3 && rc == WDG_OK; ++trial) {
+                    hip_check(hipEventRecord(a, s), "event");
+                    for (int r = 0; r < reps && rc == WDG_OK; ++r) rc = stage();
+                    hip_check(hipEventRecord(b, s), "event");
+                    hip_check(hipEventSynchronize(b), "event");
+                    float ms = 0.0f;
+                    hip_check(hipEventElapsedTime(&ms, a, b), "event");
+                    best_ms = std::min(best_ms, ms);
+                }
+                t_us = 1e3 * best_ms / reps;
+                if (rc == WDG_OK && t_us < best) {
+                    best = t_us;
+                    best_i = i;
+                }
+            }
+            if (times_us) times_us[i] = t_us;
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (rc != WDG_OK || best_i < 0) {
+            c->kernel = kernel0;
+            c->tpw = tpw0;
+            return rc != WDG_OK ? rc : fail(c, WDG_EHIP, "no stage kernel ran");
+        }
+        c->kernel = cands[best_i].kernel;
+        c->tpw = cands[best_i].tpw;
+        return WDG_OK;
+    });
+}
+
+}  // extern "C"

@@ -81,6 +81,18 @@ struct wdg_ctx {
     wdg::DevBuf frags;
     bool mfma_ok = false;
     int kernel = WDG_KERNEL_SCALAR;
+    int tpw = 2;  // tiles per workgroup of the matrix-core kernel
+    // per-element factor on dt (independent simulations sharing one launch)
+    wdg::DevBuf dt_scale;
+    bool has_dt_scale = false;
+    // captured two-step graph of wdg_step_graph and what it was captured for
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = 0.0;
+    int graph_cur = -1, graph_kernel = -1, graph_tpw = -1;
+    void* graph_bufs[3] = {nullptr, nullptr, nullptr};
+    ~wdg_ctx() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
     bool has_src = false;
     wdg_dipole dip{};
     // probes

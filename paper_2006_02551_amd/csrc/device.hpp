@@ -23,7 +23,6 @@ constexpr int kBlock = 64;   // element slots per block (one wavefront)
 constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
 constexpr int kMfmaThreads = 6 * 64;  // MFMA kernel: one wavefront per component of a 16-element tile
-constexpr int kMfmaTiles = 2;          // MFMA kernel: 16-element tiles per workgroup (1, 2 or 4)
 
 // MFMA operand fragments.  An operator with `rows` rows is cut into tiles of
 // 16 rows; for every tile t and k-step s (4 columns) there is one fragment.
@@ -65,6 +64,7 @@ struct StageParams {
     double* grad;         // [nblk_pml][3][Nq][B] sigma gradient accumulator (FP64)
     const double* cub_w;  // [Nq] cubature weights
     const double* Jk;     // [nblk][B] Jacobians
+    const double* dt_scale;  // [nblk][B] per-element factor on dt, or null (uniform dt)
     int nblk_pml, nblk, Nq;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
@@ -115,7 +115,8 @@ struct EnergyParams {
 
 // Launchers (kernels.hip, kernels_mfma.hip); return hipError_t as int.
 int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
-int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+// tpw: 16-element tiles per workgroup of the matrix-core kernel (1 or 2).
+int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s);
 // Adjoint stage on the matrix cores (kappa = 1; same (N, N_q) support as the forward).
 int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s);
 bool mfma_supported(int N, int Nq, int precision);

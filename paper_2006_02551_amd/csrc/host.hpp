@@ -50,6 +50,9 @@ struct PmlParams {
     double order, kappa_max;
 };
 
+// (d / L)^p with d the distance of x beyond [lo, hi] (0 inside; p = 0 gives a step).
+double profile_ratio(double x, double lo, double hi, double L, double p);
+
 struct Setup {
     RefElement ref;
     int K = 0, K_pml = 0;

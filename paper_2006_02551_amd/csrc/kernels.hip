@@ -217,7 +217,9 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     // ---- 6. LSERK4 stage update
     real* __restrict__ rs = static_cast<real*>(p.res);
     real* __restrict__ qo = static_cast<real*>(p.q_out);
-    const real A = static_cast<real>(p.rk_a), Bk = static_cast<real>(p.rk_b), dt = static_cast<real>(p.dt);
+    const real A = static_cast<real>(p.rk_a), Bk = static_cast<real>(p.rk_b);
+    // time step of this lane's element (a per-element scale lets independent simulations share a launch)
+    const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + lane] : p.dt);
     {
         const size_t eb = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
 #pragma unroll

@@ -8,7 +8,7 @@
 //   Out (M x 16 elements) = Op (M x K) * X (K x 16 elements)
 //
 // A tile is 16 elements (the columns), handled by six wavefronts, one per
-// field component u; a workgroup takes kMfmaTiles adjacent tiles so that its
+// field component u; a workgroup takes TPW adjacent tiles (1 or 2) so that its
 // wavefront count is a multiple of the four SIMDs of a compute unit.  The
 // reference operators are the A operands; they are stored on the host in
 // fragment order (operator tile, k-step, lane; the last tile of an N_p-row
@@ -101,7 +101,7 @@ constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
 
 // Compile-time shape of the kernel for one precision, order and number of
 // cubature tiles.
-template <typename real, int N, int QT, bool ADJ = false>
+template <typename real, int N, int QT, bool ADJ = false, int TPW = 2>
 struct Shape {
     static constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, T = 16;
     static constexpr int NF = 4 * Nfp;             // face nodes per element
@@ -132,11 +132,12 @@ struct Shape {
     static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
     static constexpr int L_FL = 6 * NFH * T * RB;
     static constexpr int L_GL = ADJ ? 3 * QMAX * T * RB : 0;  // adjoint: sigma-gradient accumulator
-    static constexpr int LDS = L_FR + kMfmaTiles * (L_TL + L_FL + L_GL);
-    // Two workgroups per compute unit (6 wavefronts per SIMD) where their LDS
-    // fits in the 160 KiB of a compute unit; the compiler then keeps the
-    // registers to that occupancy.
-    static constexpr int WAVES_PER_SIMD = 2 * LDS <= 160 * 1024 ? 6 : 1;
+    static constexpr int LDS = L_FR + TPW * (L_TL + L_FL + L_GL);
+    // Register budget: as many wavefronts per SIMD as the workgroups that fit
+    // in the 160 KiB of LDS of a compute unit bring (at most 6, 80 VGPRs).
+    static constexpr int WG_PER_CU = LDS <= 160 * 1024 ? (160 * 1024 / LDS < 1 ? 1 : 160 * 1024 / LDS) : 1;
+    static constexpr int WAVES_PER_SIMD_RAW = (WG_PER_CU * 6 * TPW + 3) / 4;
+    static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_RAW < 6 ? WAVES_PER_SIMD_RAW : 6;
 };
 
 // ADJ selects the adjoint stage (the energy-inner-product transpose of the
@@ -145,13 +146,13 @@ struct Shape {
 // writes q_base + dt L* y to q_out and adds the stage's sigma gradient to
 // p.grad.  Same staging, flux, lift and curl as the forward stage, with the
 // flux parameter negated by the caller.
-template <typename real, int N, int QT, bool KAPPA, bool ADJ>
-__global__ __launch_bounds__(kMfmaTiles * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ>::WAVES_PER_SIMD)))
+template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW>
+__global__ __launch_bounds__(TPW * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ, TPW>::WAVES_PER_SIMD)))
 void stage_mfma_kernel(StageParams p) {
     static_assert(!(ADJ && KAPPA), "the adjoint stage is written for kappa = 1");
     using M = Mma<real>;
     using v4 = typename M::v4;
-    using S = Shape<real, N, QT, ADJ>;
+    using S = Shape<real, N, QT, ADJ, TPW>;
     constexpr int QMAX = S::QMAX;
     constexpr int Np = S::Np, Nfp = S::Nfp, B = kBlock, T = S::T;
     constexpr int NF = S::NF, PT = S::PT, MR = S::MR, SP = S::SP, SQM = S::SQM, SF = S::SF, S0 = S::S0;
@@ -162,11 +163,11 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int FIT = (NFH * T + kMfmaThreads - 1) / kMfmaThreads;  // flux items per thread and round
     constexpr int RB = S::RB;
     constexpr int L_FR = S::L_FR, L_EH = S::L_EH, L_SG = S::L_SG, L_GE = S::L_GE, L_TL = S::L_TL;
-    __shared__ __attribute__((aligned(16))) char smem[L_FR + kMfmaTiles * L_TL];
-    __shared__ real fls[kMfmaTiles][6 * NFH * T];  // flux [component][face node of the round][element of the tile]
-    __shared__ real gls[ADJ ? kMfmaTiles * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
+    __shared__ __attribute__((aligned(16))) char smem[L_FR + TPW * L_TL];
+    __shared__ real fls[TPW][6 * NFH * T];  // flux [component][face node of the round][element of the tile]
+    __shared__ real gls[ADJ ? TPW * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
 
-    // Workgroup: kMfmaTiles adjacent tiles of one element block, six
+    // Workgroup: TPW adjacent tiles of one element block, six
     // wavefronts each (a multiple of four wavefronts keeps the four SIMDs of a
     // compute unit equally loaded); the operator fragments are shared.
     const int h = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kMfmaThreads);
@@ -180,7 +181,7 @@ void stage_mfma_kernel(StageParams p) {
     real* fl = fls[h];
 
     const int tile = __builtin_amdgcn_readfirstlane(
-        kMfmaTiles * remap_tile(blockIdx.x, 4 / kMfmaTiles * p.nblk_pml, 4 / kMfmaTiles * p.nblk) + h);
+        TPW * remap_tile(blockIdx.x, 4 / TPW * p.nblk_pml, 4 / TPW * p.nblk) + h);
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
     const int Nq = p.Nq;
@@ -198,7 +199,7 @@ void stage_mfma_kernel(StageParams p) {
     // ---- stage the tile into LDS (direct global->LDS loads)
     {
         const size_t row = static_cast<size_t>(B) * RB;  // bytes between rows of the blocked layout
-        stage_rows(reinterpret_cast<const char*>(p.frags), 1024, 1024, L_FR / 1024, smem, h * 6 + u, 6 * kMfmaTiles, lane);
+        stage_rows(reinterpret_cast<const char*>(p.frags), 1024, 1024, L_FR / 1024, smem, h * 6 + u, 6 * TPW, lane);
         stage_rows(reinterpret_cast<const char*>(qin + static_cast<size_t>(blk) * EHS + T * sub), row, T * RB, 6 * Np,
                    tl, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.geo) + static_cast<size_t>(blk) * kGeo * B + T * sub),
@@ -349,7 +350,9 @@ void stage_mfma_kernel(StageParams p) {
     const int ax = (u < 3) ? u : u - 3;
     const int bb = (ax == 2) ? 0 : ax + 1;
     const int cc = (ax == 0) ? 2 : ax - 1;
-    const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b), dt = static_cast<real>(p.dt);
+    const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b);
+    // time step of this lane's element (a per-element scale lets independent simulations share a launch)
+    const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + e] : p.dt);
 
     // ---- C. volume curl: +curl H (E components), -curl E (H components)
     {
@@ -583,34 +586,35 @@ void stage_mfma_kernel(StageParams p) {
     }
 }
 
-template <typename real, int N, int QT, bool K, bool ADJ = false>
+template <typename real, int N, int QT, bool K, bool ADJ, int TPW>
 int launch_t(const StageParams& p, hipStream_t s) {
-    if constexpr (Shape<real, N, QT, ADJ>::LDS > 160 * 1024) {
+    if constexpr (Shape<real, N, QT, ADJ, TPW>::LDS > 160 * 1024) {
         return static_cast<int>(hipErrorInvalidConfiguration);  // more LDS than a compute unit has
     } else {
-        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ>), dim3(4 / kMfmaTiles * p.nblk),
-                           dim3(kMfmaTiles * kMfmaThreads), 0, s, p);
+        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW>), dim3(4 / TPW * p.nblk), dim3(TPW * kMfmaThreads), 0,
+                           s, p);
         return static_cast<int>(hipGetLastError());
     }
 }
 
 template <typename real, int N, int QT>
-constexpr bool adj_fits() { return Shape<real, N, QT, true>::LDS <= 160 * 1024; }
+constexpr bool adj_fits() { return Shape<real, N, QT, true, 2>::LDS <= 160 * 1024; }
 
 template <typename real, int N, int QT>
-int launch_k(bool k, const StageParams& p, hipStream_t s) {
-    return k ? launch_t<real, N, QT, true>(p, s) : launch_t<real, N, QT, false>(p, s);
+int launch_k(bool k, int tpw, const StageParams& p, hipStream_t s) {
+    if (tpw == 1) return k ? launch_t<real, N, QT, true, false, 1>(p, s) : launch_t<real, N, QT, false, false, 1>(p, s);
+    return k ? launch_t<real, N, QT, true, false, 2>(p, s) : launch_t<real, N, QT, false, false, 2>(p, s);
 }
 
 template <typename real>
 int launch_adj(int N, int QT, const StageParams& p, hipStream_t s) {
     switch (N * 10 + QT) {
-        case 11: return launch_t<real, 1, 1, false, true>(p, s);
-        case 12: return launch_t<real, 1, 2, false, true>(p, s);
-        case 21: return launch_t<real, 2, 1, false, true>(p, s);
-        case 22: return launch_t<real, 2, 2, false, true>(p, s);
-        case 32: return launch_t<real, 3, 2, false, true>(p, s);
-        case 33: return launch_t<real, 3, 3, false, true>(p, s);
+        case 11: return launch_t<real, 1, 1, false, true, 2>(p, s);
+        case 12: return launch_t<real, 1, 2, false, true, 2>(p, s);
+        case 21: return launch_t<real, 2, 1, false, true, 2>(p, s);
+        case 22: return launch_t<real, 2, 2, false, true, 2>(p, s);
+        case 32: return launch_t<real, 3, 2, false, true, 2>(p, s);
+        case 33: return launch_t<real, 3, 3, false, true, 2>(p, s);
         default: return -1;
     }
 }
@@ -618,22 +622,22 @@ int launch_adj(int N, int QT, const StageParams& p, hipStream_t s) {
 // Order / cubature-tile combinations with a matrix-core kernel.  FP64 at
 // N = 4 would need more than the 160 KiB of LDS of a compute unit.
 template <typename real>
-int launch_r(int N, int QT, bool k, const StageParams& p, hipStream_t s) {
+int launch_r(int N, int QT, bool k, int tpw, const StageParams& p, hipStream_t s) {
     switch (N * 10 + QT) {
-        case 11: return launch_k<real, 1, 1>(k, p, s);
-        case 12: return launch_k<real, 1, 2>(k, p, s);
-        case 21: return launch_k<real, 2, 1>(k, p, s);
-        case 22: return launch_k<real, 2, 2>(k, p, s);
-        case 32: return launch_k<real, 3, 2>(k, p, s);
-        case 33: return launch_k<real, 3, 3>(k, p, s);
+        case 11: return launch_k<real, 1, 1>(k, tpw, p, s);
+        case 12: return launch_k<real, 1, 2>(k, tpw, p, s);
+        case 21: return launch_k<real, 2, 1>(k, tpw, p, s);
+        case 22: return launch_k<real, 2, 2>(k, tpw, p, s);
+        case 32: return launch_k<real, 3, 2>(k, tpw, p, s);
+        case 33: return launch_k<real, 3, 3>(k, tpw, p, s);
         default: return -1;
     }
 }
 
-int launch_r4(int QT, bool k, const StageParams& p, hipStream_t s) {
+int launch_r4(int QT, bool k, int tpw, const StageParams& p, hipStream_t s) {
     switch (QT) {
-        case 3: return launch_k<float, 4, 3>(k, p, s);
-        case 4: return launch_k<float, 4, 4>(k, p, s);
+        case 3: return launch_k<float, 4, 3>(k, tpw, p, s);
+        case 4: return launch_k<float, 4, 4>(k, tpw, p, s);
         default: return -1;
     }
 }
@@ -668,16 +672,16 @@ bool mfma_supported(int N, int Nq, int precision) {
 
 int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s) {
     const int QT = (p.Nq + 15) / 16;
-    if (N == 4) return precision == 0 ? -1 : (QT == 3 ? launch_t<float, 4, 3, false, true>(p, s)
-                                                      : QT == 4 ? launch_t<float, 4, 4, false, true>(p, s) : -1);
+    if (N == 4) return precision == 0 ? -1 : (QT == 3 ? launch_t<float, 4, 3, false, true, 2>(p, s)
+                                                      : QT == 4 ? launch_t<float, 4, 4, false, true, 2>(p, s) : -1);
     return precision == 0 ? launch_adj<double>(N, QT, p, s) : launch_adj<float>(N, QT, p, s);
 }
 
-int launch_stage_mfma(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s) {
+int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s) {
     const int QT = (p.Nq + 15) / 16;
-    if (precision == 0) return launch_r<double>(N, QT, has_kappa, p, s);
-    if (N == 4) return launch_r4(QT, has_kappa, p, s);
-    return launch_r<float>(N, QT, has_kappa, p, s);
+    if (precision == 0) return launch_r<double>(N, QT, has_kappa, tpw, p, s);
+    if (N == 4) return launch_r4(QT, has_kappa, tpw, p, s);
+    return launch_r<float>(N, QT, has_kappa, tpw, p, s);
 }
 
 }  // namespace wdg

@@ -17,8 +17,11 @@
 //    exactly through their integer barycentric weights on the shared global
 //    vertices, so no coordinate tolerance is involved;
 //  * PML elements come first, then interior elements; inside each class the
-//    elements are ordered along a Morton curve of their centroids and packed
-//    into blocks of B element slots.
+//    elements are grouped by face-connected component (numbered in order of
+//    their lowest element index), ordered along a Morton curve of their
+//    centroids within a component, and packed into blocks of B element slots.
+//    A single mesh is one component; a batch of disjoint meshes that overlap
+//    in space keeps each mesh contiguous, so face neighbours stay close.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -48,13 +51,13 @@ uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
     return x;
 }
 
+}  // namespace
+
 double profile_ratio(double x, double lo, double hi, double L, double p) {
     const double d = std::max(0.0, std::max(x - hi, lo - x));
     if (d <= 0.0) return 0.0;
     return std::pow(d / L, p);
 }
-
-}  // namespace
 
 Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, int nq, const double* rst,
                   const double* w, const PmlParams& pml, double flux_alpha) {
@@ -259,14 +262,36 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
         S.is_pml[k] = any ? 1 : 0;
     }
 
-    // ---- ordering: PML class first, Morton order of centroids within each class
+    // ---- ordering: PML class first, then component, then Morton order of centroids
+    std::vector<int> comp(K, -1);
+    {
+        std::vector<int> stack;
+        int ncomp = 0;
+        for (int k0 = 0; k0 < K; ++k0) {
+            if (comp[k0] >= 0) continue;
+            comp[k0] = ncomp;
+            stack.assign(1, k0);
+            while (!stack.empty()) {
+                const int k = stack.back();
+                stack.pop_back();
+                for (int f = 0; f < 4; ++f) {
+                    const int k2 = S.etoe[4 * static_cast<size_t>(k) + f];
+                    if (comp[k2] < 0) {
+                        comp[k2] = ncomp;
+                        stack.push_back(k2);
+                    }
+                }
+            }
+            ++ncomp;
+        }
+    }
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int i = 0; i < nv; ++i)
         for (int d = 0; d < 3; ++d) {
             lo[d] = std::min(lo[d], vxyz[3 * i + d]);
             hi[d] = std::max(hi[d], vxyz[3 * i + d]);
         }
-    std::vector<std::pair<uint64_t, int>> pml_list, int_list;
+    std::vector<std::pair<std::pair<int, uint64_t>, int>> pml_list, int_list;
     for (int k = 0; k < K; ++k) {
         uint64_t code = 0;
         for (int d = 0; d < 3; ++d) {
@@ -276,7 +301,7 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
             const uint64_t iu = static_cast<uint64_t>(std::min(std::max(u, 0.0), 1.0) * 2097151.0);
             code |= spread3(iu) << d;
         }
-        (S.is_pml[k] ? pml_list : int_list).push_back({code, k});
+        (S.is_pml[k] ? pml_list : int_list).push_back({{comp[k], code}, k});
     }
     std::sort(pml_list.begin(), pml_list.end());
     std::sort(int_list.begin(), int_list.end());

@@ -20,6 +20,8 @@ Each recipe is a plain dict:
   probes      probe points [n, 3] (or None)
   steps       number of LSERK4 steps
   shell       (differentiation form) box shell of the loss: outer_lo/hi, inner_lo/hi
+  batch       (batching form) nsim, n_range, sigma_range, orders, seed of the per-simulation draws;
+              the recipe's mesh box, PML box and thickness are shared
   cfl         dt = cfl / ((N+1)^2 * max_{k,f} Fscale_{k,f})
 """
 from __future__ import annotations
@@ -62,6 +64,15 @@ CONFIGS = {
            "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [40.0] * 3,
                    "order": 2.0, "kappa_max": 1.0},
            "alpha": 1.0, "init": None, "source": _DIPOLE, "probes": _CUBE8, "steps": 2000, "cfl": CFL},
+    # Batching form: 32 independent simulations in one launch, meshes 8^3 x 6 .. 24^3 x 6, each with its own
+    # sigma_max in [10, 50] and profile order in {2, 3, 4}, N=3, FP32, 500 steps, a Gaussian Ez pulse each.
+    "c4": {"name": "c4", "N": 3, "cub_degree": 6,
+           "mesh": {"n": 0, "lo": -1.5, "hi": 1.5, "perturb": 0.1, "seed": 0},
+           "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [30.0] * 3,
+                   "order": 3.0, "kappa_max": 1.0},
+           "alpha": 1.0, "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.25},
+           "source": None, "probes": None, "steps": 500, "cfl": CFL,
+           "batch": {"nsim": 32, "n_range": [8, 24], "sigma_range": [10.0, 50.0], "orders": [2, 3, 4], "seed": 0}},
     # Differentiation form: the 48,000-tet N=3 mesh and cubic profile of c2, a Gaussian Ez pulse at the
     # origin that reaches the layer within the 500 steps, loss = time-integrated energy in the shell
     # 0.1 inside the PML interface.

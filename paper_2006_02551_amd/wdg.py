@@ -57,7 +57,7 @@ class wdg_dims_t(C.Structure):
                 ("Nfp", C.c_int32), ("Nq", C.c_int32), ("block", C.c_int32), ("nblk_pml", C.c_int32),
                 ("nblk", C.c_int32), ("precision", C.c_int32), ("has_kappa", C.c_int32),
                 ("state_bytes", C.c_int64), ("dt_unit", C.c_double), ("time", C.c_double), ("steps", C.c_int64),
-                ("kernel", C.c_int32)]
+                ("kernel", C.c_int32), ("tiles", C.c_int32)]
 
 
 class wdg_dipole(C.Structure):
@@ -108,6 +108,11 @@ wdg_node_coords = _sig("wdg_node_coords", C.c_int32, _ctx, _dp)
 wdg_reference_op = _sig("wdg_reference_op", C.c_int32, _ctx, C.c_int32, _dp)
 wdg_element_info = _sig("wdg_element_info", C.c_int32, _ctx, _dp, _dp, _dp, _ip, _ip, _ip)
 wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem_t))
+wdg_set_tiles = _sig("wdg_set_tiles", C.c_int32, _ctx, C.c_int32)
+wdg_autotune = _sig("wdg_autotune", C.c_int32, _ctx, C.c_int32, _dp, C.c_void_p)
+wdg_step_graph = _sig("wdg_step_graph", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
+wdg_set_dt_scale = _sig("wdg_set_dt_scale", C.c_int32, _ctx, _dp)
+wdg_set_sigma_profile = _sig("wdg_set_sigma_profile", C.c_int32, _ctx, _ip, C.c_int32, _dp, _dp)
 wdg_set_sigma_q = _sig("wdg_set_sigma_q", C.c_int32, _ctx, _dp)
 wdg_get_sigma_q = _sig("wdg_get_sigma_q", C.c_int32, _ctx, _dp)
 wdg_cubature_points = _sig("wdg_cubature_points", C.c_int32, _ctx, _dp)
@@ -229,6 +234,14 @@ class Context:
         _check(wdg_cubature_points(self.h, _ptr(out)), self.h)
         return out
 
+    def set_sigma_profile(self, group, sigma_max, order):
+        """Per-group profiles: group [K] int, sigma_max [G, 3], order [G]."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        sm = _f64(np.asarray(sigma_max, dtype=np.float64).reshape(-1, 3))
+        od = _f64(np.asarray(order, dtype=np.float64).reshape(-1))
+        assert g.shape == (self.dims.K,) and len(sm) == len(od)
+        _check(wdg_set_sigma_profile(self.h, _ptr(g, _ip), len(od), _ptr(sm), _ptr(od)), self.h)
+
     def get_sigma_q(self):
         d = self.dims
         out = np.zeros((d.K, d.Nq, 3))
@@ -308,6 +321,30 @@ class Simulation(Context):
 
     def step(self, dt, nsteps, stream=None):
         _check(wdg_step(self.h, float(dt), int(nsteps), self._stream(stream)), self.h)
+
+    def step_graph(self, dt, nsteps, stream=None):
+        """Like step, replaying a captured two-step HIP graph (needs a non-default stream)."""
+        _check(wdg_step_graph(self.h, float(dt), int(nsteps), self._stream(stream)), self.h)
+
+    def set_tiles(self, tiles):
+        _check(wdg_set_tiles(self.h, int(tiles)), self.h)
+        self.dims = self.get_dims()
+
+    def autotune(self, reps=5, stream=None):
+        """Times the stage kernels and keeps the fastest; returns us per launch
+        {'scalar': t, 'mfma_1tile': t, 'mfma_2tiles': t} (None where unavailable)."""
+        t = np.zeros(3)
+        _check(wdg_autotune(self.h, int(reps), _ptr(t), self._stream(stream)), self.h)
+        self.dims = self.get_dims()
+        return {k: (None if v < 0 else float(v)) for k, v in zip(("scalar", "mfma_1tile", "mfma_2tiles"), t)}
+
+    def set_dt_scale(self, scale):
+        if scale is None:
+            _check(wdg_set_dt_scale(self.h, None), self.h)
+            return
+        sc = _f64(np.asarray(scale, dtype=np.float64).reshape(-1))
+        assert sc.shape == (self.dims.K,)
+        _check(wdg_set_dt_scale(self.h, _ptr(sc)), self.h)
 
     def rhs(self, t, stream=None):
         _check(wdg_rhs(self.h, float(t), self._stream(stream)), self.h)

@@ -157,3 +157,28 @@ def test_loss_gradient_needs_device_state():
     assert wdg.wdg_loss_gradient(ctx.h, 0.01, 5, C.byref(sh), 0, C.byref(loss), None, None, None) == wdg.WDG_ESTATE
     assert wdg.wdg_loss_gradient(ctx.h, 0.01, -1, C.byref(sh), 0, C.byref(loss), None, None, None) == wdg.WDG_EINVAL
     assert wdg.wdg_shell_energy(ctx.h, C.byref(sh), C.byref(loss), None) == wdg.WDG_ESTATE
+
+
+def test_batch_recipe_and_group_profiles():
+    cfg = inputs.config("c4", batch={"nsim": 3, "n_range": [2, 3], "sigma_range": [10.0, 50.0], "orders": [2, 3, 4],
+                                     "seed": 4})
+    rec = inputs.batch_recipe(cfg["batch"])
+    assert rec == inputs.batch_recipe(cfg["batch"])  # seeded
+    meshes = inputs.batch_meshes(cfg, rec)
+    vx, ev, group, offs = inputs.concat_meshes(meshes)
+    # disjoint vertex sets per simulation
+    for g in range(3):
+        used = np.unique(ev[offs[g]:offs[g + 1]])
+        assert used.min() >= sum(len(m[0]) for m in meshes[:g]) and used.max() < sum(len(m[0]) for m in meshes[:g + 1])
+    rule = inputs.load_rule(cfg["cub_degree"])
+    pml = dict(cfg["pml"], sigma_max=[1.0] * 3, order=2.0)
+    ctx = wdg.Context(vx, ev, cfg["N"], rule, pml, host_only=True)
+    ctx.set_sigma_profile(group, [[r["sigma_max"]] * 3 for r in rec], [r["order"] for r in rec])
+    sig = ctx.get_sigma_q()
+    for g, r in enumerate(rec):
+        alone = wdg.Context(*meshes[g], cfg["N"], rule, dict(cfg["pml"], sigma_max=[r["sigma_max"]] * 3, order=r["order"]),
+                            host_only=True)
+        assert np.array_equal(sig[offs[g]:offs[g + 1]], alone.get_sigma_q())
+        assert np.array_equal(ctx.element_info()["is_pml"][offs[g]:offs[g + 1]], alone.element_info()["is_pml"])
+    with pytest.raises(wdg.WdgError):
+        ctx.set_sigma_profile(group, [[1.0] * 3], [2.0])  # group index out of range
