@@ -17,6 +17,8 @@ Modules, in the order the method is built:
               curl operator of eqs. (10)-(17).
 * ``brute``   the direct stored-mass-matrix scheme, eqs. (10)-(15)
               (the paper's "SV-paved" method), for comparison.
+* ``ec``      element-constant coefficients (the paper's "EC-paved"
+              configuration, Sec. III).
 * ``lserk``   five-stage fourth-order low-storage Runge-Kutta.
 * ``readout`` energy and point probes.
 * ``run``     assembles a whole simulation from inputs.

@@ -10,6 +10,7 @@ import numpy as np
 
 from . import lserk
 from .brute import BruteOperator
+from .ec import ECOperator
 from .mesh import Mesh
 from .readout import energy, probe, probe_weights
 from .refel import RefElement
@@ -17,12 +18,17 @@ from .rhs import Operator
 
 
 class Simulation:
-    def __init__(self, cfg: dict, vxyz, etov, rst, w, brute: bool = False, sigma_q=None):
+    def __init__(self, cfg: dict, vxyz, etov, rst, w, brute: bool = False, sigma_q=None, scheme: str = "waa",
+                 brute_points: int = 9):
         self.cfg = cfg
         self.ref = RefElement(cfg["N"], rst, w)
         self.mesh = Mesh(vxyz, etov, self.ref)
-        if brute:
-            self.op = BruteOperator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"))
+        scheme = "direct" if brute else scheme
+        if scheme == "direct":
+            self.op = BruteOperator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"),
+                                    quad_points=brute_points)
+        elif scheme == "ec":
+            self.op = ECOperator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"))
         else:
             self.op = Operator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"), sigma_q=sigma_q)
         self.dt = float(cfg["cfl"]) / ((cfg["N"] + 1) ** 2 * np.max(self.mesh.Fscale))

@@ -110,6 +110,28 @@ def load_rule(degree: int):
     return np.ascontiguousarray(data[:, :3]), np.ascontiguousarray(data[:, 3])
 
 
+def product_rule(n: int):
+    """Conical product rule with n^3 points on the reference tetrahedron, exact to polynomial degree 2n - 1.
+
+    Collapsed coordinates (a, b, c) in [-1, 1]^3 map to the tetrahedron with vertices (-1,-1,-1), (1,-1,-1),
+    (-1,1,-1), (-1,-1,1) by r = (1+a)(1-b)(1-c)/4 - 1, s = (1+b)(1-c)/2 - 1, t = c, whose Jacobian is
+    (1-b)(1-c)^2/8; Gauss rules for the weights 1, (1-b) and (1-c)^2 absorb it.  Used for integrals
+    whose integrand is not a low-degree polynomial (profile-weighted mass matrices).
+    Returns (rst [n^3, 3], w [n^3]); the weights sum to 4/3.
+    """
+    from scipy.special import roots_jacobi
+
+    a, wa = roots_jacobi(n, 0.0, 0.0)
+    b, wb = roots_jacobi(n, 1.0, 0.0)
+    c, wc = roots_jacobi(n, 2.0, 0.0)
+    A, Bc, Cc = np.meshgrid(a, b, c, indexing="ij")
+    W = np.einsum("i,j,k->ijk", wa, wb, wc) / 8.0
+    r = (1.0 + A) * (1.0 - Bc) * (1.0 - Cc) / 4.0 - 1.0
+    s = (1.0 + Bc) * (1.0 - Cc) / 2.0 - 1.0
+    rst = np.stack([r.ravel(), s.ravel(), Cc.ravel()], axis=1)
+    return np.ascontiguousarray(rst), np.ascontiguousarray(W.ravel())
+
+
 def gaussian_fields(cfg: dict, xnodes: np.ndarray) -> np.ndarray:
     """Initial state [K, 12, N_p] from node coordinates xnodes [K, N_p, 3]."""
     K, Np, _ = xnodes.shape
