@@ -101,6 +101,7 @@ typedef struct wdg_dims_t {
     int64_t steps;       /* steps taken since creation / last set_fields */
     int32_t kernel;      /* active stage-kernel variant (WDG_KERNEL_*) */
     int32_t tiles;       /* 16-element tiles per workgroup of the matrix-core kernel (1 or 2) */
+    int32_t pml_scheme;  /* active PML scheme (WDG_PML_*) */
 } wdg_dims_t;
 
 /* Gaussian-modulated dipole current, added to dE/dt as -J:
@@ -126,6 +127,8 @@ typedef struct wdg_mem_t {
     int64_t operators;       /* reference operators */
     int64_t paper_direct;    /* 15 N_p^2 K_pml words of the direct method */
     int64_t paper_waa;       /* 15 N_q K_pml + 2 N_p N_q words of the paper's WAA storage */
+    int64_t scheme_data;     /* device bytes of the direct scheme's matrices or the element-constant
+                                coefficients (0 for the weight-adjusted scheme) */
 } wdg_mem_t;
 
 /* Version: major*10000 + minor*100 + patch. */
@@ -189,6 +192,43 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
  * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64,
  * FP32 only). */
 int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
+
+/* ---- PML schemes compared with the weight-adjusted one ------------------- */
+
+/* How the PML terms of eqs. (10)-(13) are evaluated.
+ *   WDG_PML_WAA (default): the weight-adjusted scheme of eqs. (26)-(29), sigma
+ *     (and kappa) at the cubature points, reference operators only.
+ *   WDG_PML_DIRECT: the direct scheme with exact weighted mass matrices (the
+ *     smoothly-varying implementation the paper compares against in Sec. I,
+ *     the memory count after eq. (29) and Table I, "SV-paved"): for every PML
+ *     element and axis u the library integrates the five mass matrices of
+ *     eq. (15) weighted by a, b, c, d, 1/kappa of eq. (9), evaluated from the
+ *     method's profile at the points of the rule passed here, and stores the
+ *     products (M^a)^-1 M_k, (M^a)^-1 M^b, (M^a)^-1 M^c, M_k^-1 M^{1/kappa},
+ *     M_k^-1 M^d: 15 N_p^2 words per PML element in the state's precision, read
+ *     by every stage.
+ *   WDG_PML_CONSTANT: element-constant coefficients (Sec. III, configuration
+ *     (i), "EC-paved"): sigma_u and kappa_u of each PML element taken at its
+ *     node farthest beyond the interface along +-u; the weighted mass matrices
+ *     are then multiples of M_k and the PML terms are pointwise.
+ * Elements carry auxiliary fields on the same set in every scheme (a nonzero
+ * sigma or kappa != 1 at a cubature point).  The direct and element-constant
+ * schemes run on the scalar-operand kernel. */
+#define WDG_PML_WAA 0
+#define WDG_PML_DIRECT 1
+#define WDG_PML_CONSTANT 2
+
+/* Selects the PML scheme.  For WDG_PML_DIRECT, nr points rst [nr][3] on the
+ * reference tetrahedron (vertices (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1))
+ * with weights w [nr] integrate the weighted mass matrices (the weights are not
+ * polynomial inside elements cut by the interface, so a rule well above degree
+ * 2N is advisable); the other schemes ignore nr, rst and w.  Host setup in FP64
+ * on up to 16 threads, then an upload; the previous scheme's data are freed.
+ * Errors: WDG_EINVAL for an unknown scheme or a bad rule, WDG_ESTATE for a
+ * host-only context or when sigma at the cubature points was replaced
+ * (wdg_set_sigma_q, wdg_set_sigma_profile): these schemes sample the method's
+ * profile, WDG_ENOMEM when the matrices do not fit. */
+int32_t wdg_set_pml_scheme(wdg_ctx* ctx, int32_t scheme, int32_t nr, const double* rst, const double* w);
 
 /* Tiles of 16 elements per workgroup of the matrix-core kernel: 1 or 2 (the
  * default).  Results do not depend on it. */

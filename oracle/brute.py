@@ -32,12 +32,23 @@ from .rhs import Operator
 
 
 class BruteOperator(Operator):
-    def __init__(self, mesh, ref, pml, alpha=1.0, source=None, quad_points: int = 9):
+    """rule: optional (rst [nr, 3], w [nr]) on the reference tetrahedron for the weighted mass matrices
+    (an input like the cubature rule of the weight-adjusted scheme; default: the conical product rule with
+    quad_points points per direction).  elements: optional subset of element indices; the stored matrices
+    are then formed for the PML elements of that subset only, and rhs(..., el) accepts only elements
+    whose PML terms are stored."""
+
+    def __init__(self, mesh, ref, pml, alpha=1.0, source=None, quad_points: int = 9, elements=None, rule=None):
         super().__init__(mesh, ref, pml, alpha=alpha, source=source)
-        xr, wr = collapsed_rule_tet(quad_points)
+        if rule is None:
+            xr, wr = collapsed_rule_tet(quad_points)
+        else:
+            xr, wr = np.asarray(rule[0], dtype=np.float64), np.asarray(rule[1], dtype=np.float64)
         L = ref.lagrange(xr)  # [nr, Np]
-        pe = self.pml_elems
-        xp = mesh.map_points(xr)[pe]  # [Kp, nr, 3]
+        pe = self.pml_elems if elements is None else np.intersect1d(self.pml_elems, np.asarray(elements))
+        self.brute_index = np.full(len(self.pml_elems), -1)
+        self.brute_index[np.searchsorted(self.pml_elems, pe)] = np.arange(len(pe))
+        xp = mesh.v[pe][:, None, 0, :] + np.einsum("kij,nj->kni", mesh.Jm[pe], xr + 1.0)  # [Kp, nr, 3]
         sigma, kappa = sigma_kappa(xp, pml)
         a, b, c, d, kap = tensors(sigma, kappa)
         J = mesh.J[pe]
@@ -53,6 +64,9 @@ class BruteOperator(Operator):
         self.Mk = J[:, None, None] * ref.M[None]
 
     def pml_update(self, f, P, R, p):
+        p = self.brute_index[p]
+        if np.any(p < 0):
+            raise ValueError("the stored matrices of these PML elements were not formed")
         Mk = self.Mk[p][:, None]  # [k, 1, Np, Np]
         rhs_f = np.einsum("kuij,kuj->kui", np.broadcast_to(Mk, self.Ma[p].shape), R) \
             - np.einsum("kuij,kuj->kui", self.Mb[p], f) - np.einsum("kuij,kuj->kui", self.Mc[p], P)

@@ -17,9 +17,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdg.so")
 ARCH = "gfx950"
 
-SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "batch.cpp", "kernels.hip", "kernels_mfma.hip", "kernels_adjoint.hip"]
+SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "batch.cpp", "pml_schemes.cpp", "kernels.hip", "kernels_mfma.hip",
+           "kernels_adjoint.hip"]
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(HERE, '..', 'include')}"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", f"-I{os.path.join(HERE, '..', 'include')}"]
 # Packed FP32 instructions are disabled for all device code.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast", "-munsafe-fp-atomics"]
@@ -49,7 +50,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

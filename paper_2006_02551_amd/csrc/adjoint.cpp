@@ -146,6 +146,7 @@ extern "C" {
 
 int32_t wdg_set_sigma_q(wdg_ctx* c, const double* sigma) {
     if (!c || !sigma) return WDG_EINVAL;
+    if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_ESTATE, "sigma at the cubature points is used by the weight-adjusted scheme only");
     return guarded(c, [&]() -> int {
         Setup& S = c->S;
         const size_t n = static_cast<size_t>(S.K) * S.ref.Nq * 3;
@@ -156,6 +157,7 @@ int32_t wdg_set_sigma_q(wdg_ctx* c, const double* sigma) {
                 if (!S.is_pml[k] && v != 0.0) return fail(c, WDG_EINVAL, "sigma must stay zero outside the PML elements");
             }
         S.sigma.assign(sigma, sigma + n);
+        c->sigma_custom = true;
         if (!c->host_only) upload_coefficients(c);
         return WDG_OK;
     });
@@ -196,6 +198,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
     const Setup& S = c->S;
     if (S.has_kappa) return fail(c, WDG_EINVAL, "the adjoint needs kappa = 1");
     if (c->has_dt_scale) return fail(c, WDG_EINVAL, "the adjoint needs one time step for all elements");
+    if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_EINVAL, "the adjoint is built for the weight-adjusted scheme");
     if (!adjoint_supported(S.ref.N, S.ref.Nq, c->precision))
         return fail(c, WDG_EINVAL, "no adjoint kernel for this order, rule size and precision");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -80,6 +80,7 @@ void upload_coefficients(wdg_ctx* c) {
                 if (S.has_kappa) kp[di] = S.kappa[(static_cast<size_t>(k) * Nq + q) * 3 + d];
             }
     }
+    c->drop_graph();
     c->sigma.upload(to_real(sg, c->precision).data(), sg.size() * c->rsize);
     if (S.has_kappa) c->kappa.upload(to_real(kp, c->precision).data(), kp.size() * c->rsize);
 }
@@ -224,6 +225,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.src = c->src.p;
     p.frags = c->frags.p;
     p.dt_scale = c->has_dt_scale ? static_cast<const double*>(c->dt_scale.p) : nullptr;
+    p.pml_mats = c->pml_mats.p;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;
@@ -238,8 +240,10 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
         const double tt = t - d.t0;
         p.src_g = d.amplitude * std::sin(2.0 * M_PI * d.f0 * tt) * std::exp(-(tt / d.tau) * (tt / d.tau));
     }
-    const int e = c->kernel == WDG_KERNEL_MFMA ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, c->tpw, p, stream)
-                                               : launch_stage(c->precision, S.ref.N, S.has_kappa, p, stream);
+    // the matrix-core kernel implements the weight-adjusted scheme only
+    const int e = (c->kernel == WDG_KERNEL_MFMA && c->pml_scheme == WDG_PML_WAA)
+                      ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, c->tpw, p, stream)
+                      : launch_stage(c->precision, S.ref.N, S.has_kappa, c->pml_scheme, p, stream);
     if (e != 0) return fail(c, WDG_EHIP, std::string("stage launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
     return WDG_OK;
 }
@@ -331,8 +335,9 @@ int32_t wdg_get_dims(const wdg_ctx* c, wdg_dims_t* o) {
     o->dt_unit = S.dt_unit;
     o->time = c->t;
     o->steps = c->steps;
-    o->kernel = c->kernel;
+    o->kernel = c->pml_scheme == WDG_PML_WAA ? c->kernel : WDG_KERNEL_SCALAR;  // the kernel that runs
     o->tiles = c->tpw;
+    o->pml_scheme = c->pml_scheme;
     return WDG_OK;
 }
 
@@ -466,6 +471,7 @@ int32_t wdg_set_dipole(wdg_ctx* c, const wdg_dipole* d) {
                 }
             }
         }
+        c->drop_graph();
         c->src.upload(to_real(src, c->precision).data(), src.size() * c->rsize);
         hip_check(hipMemcpy(c->src_slot.p, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice), "src");
         c->dip = *d;
@@ -627,6 +633,7 @@ int32_t wdg_memory_report(const wdg_ctx* c, wdg_mem_t* o) {
     o->operators = (3 * Np * Np + Np * 4 * S.ref.Nfp + 2 * Np * Nq) * r;
     o->paper_direct = 15 * Np * Np * static_cast<int64_t>(S.K_pml) * 8;
     o->paper_waa = (15 * Nq * static_cast<int64_t>(S.K_pml) + 2 * Np * Nq) * 8;
+    o->scheme_data = static_cast<int64_t>(c->pml_mats.bytes);
     return WDG_OK;
 }
 

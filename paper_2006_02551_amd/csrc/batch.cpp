@@ -50,6 +50,7 @@ int32_t wdg_set_dt_scale(wdg_ctx* c, const double* scale) {
     if (c->host_only) return fail(c, WDG_ESTATE, "host-only context");
     return guarded(c, [&]() -> int {
         const Setup& S = c->S;
+        c->drop_graph();
         if (!scale) {
             c->has_dt_scale = false;
             c->dt_scale.alloc(0);
@@ -68,6 +69,7 @@ int32_t wdg_set_dt_scale(wdg_ctx* c, const double* scale) {
 
 int32_t wdg_set_sigma_profile(wdg_ctx* c, const int32_t* group, int32_t ngroups, const double* sigma_max, const double* order) {
     if (!c || !group || ngroups <= 0 || !sigma_max || !order) return WDG_EINVAL;
+    if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_ESTATE, "per-group profiles are used by the weight-adjusted scheme only");
     return guarded(c, [&]() -> int {
         Setup& S = c->S;
         if (S.has_kappa) return fail(c, WDG_EINVAL, "per-group profiles need kappa = 1");
@@ -90,6 +92,7 @@ int32_t wdg_set_sigma_profile(wdg_ctx* c, const int32_t* group, int32_t ngroups,
                 }
         }
         S.sigma.swap(sig);
+        c->sigma_custom = true;
         if (!c->host_only) upload_coefficients(c);
         return WDG_OK;
     });
@@ -106,13 +109,10 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
         const int pairs = nsteps / 2;
         if (pairs > 0) {
             const bool same = c->graph && c->graph_dt == dt && c->graph_cur == c->cur && c->graph_kernel == c->kernel &&
-                              c->graph_tpw == c->tpw && c->graph_bufs[0] == c->q[0] && c->graph_bufs[1] == c->q[1] &&
+                              c->graph_tpw == c->tpw && c->graph_scheme == c->pml_scheme && c->graph_bufs[0] == c->q[0] && c->graph_bufs[1] == c->q[1] &&
                               c->graph_bufs[2] == c->res;
             if (!same) {
-                if (c->graph) {
-                    hip_check(hipGraphExecDestroy(c->graph), "graph destroy");
-                    c->graph = nullptr;
-                }
+                c->drop_graph();
                 // Capture two steps (ten stage launches): the buffer roles are
                 // back where they started, so one graph serves every pair.
                 const int cur0 = c->cur;
@@ -139,6 +139,7 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
                 c->graph_cur = c->cur;
                 c->graph_kernel = c->kernel;
                 c->graph_tpw = c->tpw;
+                c->graph_scheme = c->pml_scheme;
                 c->graph_bufs[0] = c->q[0];
                 c->graph_bufs[1] = c->q[1];
                 c->graph_bufs[2] = c->res;
@@ -171,7 +172,8 @@ int32_t wdg_autotune(wdg_ctx* c, int32_t reps, double* times_us, void* hip_strea
         int rc = WDG_OK;
         for (int i = 0; i < 3 && rc == WDG_OK; ++i) {
             double t_us = -1.0;
-            if (cands[i].kernel != WDG_KERNEL_MFMA || c->mfma_ok) {
+            // the matrix-core kernel runs the weight-adjusted scheme only
+            if (cands[i].kernel != WDG_KERNEL_MFMA || (c->mfma_ok && c->pml_scheme == WDG_PML_WAA)) {
                 c->kernel = cands[i].kernel;
                 c->tpw = cands[i].tpw;
                 // a stage as in the middle of a step: reads and writes the residual,

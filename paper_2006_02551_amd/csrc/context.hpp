@@ -82,16 +82,25 @@ struct wdg_ctx {
     bool mfma_ok = false;
     int kernel = WDG_KERNEL_SCALAR;
     int tpw = 2;  // tiles per workgroup of the matrix-core kernel
+    // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored
+    // matrices or the element-constant coefficients (empty for the weight-adjusted scheme)
+    int pml_scheme = WDG_PML_WAA;
+    wdg::DevBuf pml_mats;
+    bool sigma_custom = false;  // sigma at the cubature points no longer follows the method's profile
     // per-element factor on dt (independent simulations sharing one launch)
     wdg::DevBuf dt_scale;
     bool has_dt_scale = false;
     // captured two-step graph of wdg_step_graph and what it was captured for
     hipGraphExec_t graph = nullptr;
     double graph_dt = 0.0;
-    int graph_cur = -1, graph_kernel = -1, graph_tpw = -1;
+    int graph_cur = -1, graph_kernel = -1, graph_tpw = -1, graph_scheme = -1;
     void* graph_bufs[3] = {nullptr, nullptr, nullptr};
-    ~wdg_ctx() {
+    ~wdg_ctx() { drop_graph(); }
+    // A captured graph holds the device addresses of every buffer a stage reads;
+    // whatever reallocates one of them drops the graph.
+    void drop_graph() {
         if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
     }
     bool has_src = false;
     wdg_dipole dip{};

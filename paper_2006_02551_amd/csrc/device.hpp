@@ -11,6 +11,12 @@
 //                                   bitwise complement of the own offset at a
 //                                   PEC wall
 //   sigma    [nblk_pml][3][Nq][B]   (kappa likewise when it is not one)
+//   PML terms of the other schemes (scalar-operand kernel only):
+//     direct            [nblk_pml][3 axes][5][Np][Np][B]  per element and axis u the
+//                       products (M^a)^-1 M_k, (M^a)^-1 M^b, (M^a)^-1 M^c,
+//                       M_k^-1 M^{1/kappa}, M_k^-1 M^d of the weighted mass
+//                       matrices of eq. (15) (row i, column j)
+//     element-constant  [nblk_pml][6][B]  sigma_x sigma_y sigma_z kappa_x kappa_y kappa_z
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +29,10 @@ constexpr int kBlock = 64;   // element slots per block (one wavefront)
 constexpr int kGeo = 25;     // geometry words per element slot
 constexpr int kThreads = 6 * kBlock;  // one wavefront per field component
 constexpr int kMfmaThreads = 6 * 64;  // MFMA kernel: one wavefront per component of a 16-element tile
+
+// How the PML terms of eqs. (10)-(13) are evaluated (the values match WDG_PML_* of the C ABI).
+enum PmlMode : int { kPmlWaa = 0, kPmlDirect = 1, kPmlConstant = 2 };
+constexpr int kDirectMats = 5;  // stored products per element and axis
 
 // MFMA operand fragments.  An operator with `rows` rows is cut into tiles of
 // 16 rows; for every tile t and k-step s (4 columns) there is one fragment.
@@ -65,6 +75,7 @@ struct StageParams {
     const double* cub_w;  // [Nq] cubature weights
     const double* Jk;     // [nblk][B] Jacobians
     const double* dt_scale;  // [nblk][B] per-element factor on dt, or null (uniform dt)
+    const void* pml_mats;    // direct matrices or element-constant coefficients (see the layout above)
     int nblk_pml, nblk, Nq;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
@@ -114,7 +125,8 @@ struct EnergyParams {
 };
 
 // Launchers (kernels.hip, kernels_mfma.hip); return hipError_t as int.
-int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s);
+// pml_mode: PmlMode; the direct and element-constant schemes ignore has_kappa (kappa is in their data).
+int launch_stage(int precision, int N, bool has_kappa, int pml_mode, const StageParams& p, hipStream_t s);
 // tpw: 16-element tiles per workgroup of the matrix-core kernel (1 or 2).
 int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s);
 // Adjoint stage on the matrix cores (kappa = 1; same (N, N_q) support as the forward).

@@ -20,6 +20,17 @@
 //   5. rhs_f = P_q a^{-1} V_q w       (weight-adjusted inverse mass, eq. (21))
 //   6. res = A res + dt rhs;  q_out = q_in + B res             (LSERK4)
 // Interior blocks skip 1 and 5 (rhs_f = w, no auxiliary fields).
+//
+// The same kernel evaluates two other PML schemes for comparison:
+// * direct (stored matrices, eqs. (10)-(15) with exact weighted mass
+//   matrices): 1 only loads f and P; 5 becomes, row by row,
+//     rhs_f = G_1 w - G_2 f - G_3 P,   rhs_P = G_4 f - G_5 P
+//   with the five per-element N_p x N_p products of the layout in device.hpp,
+//   streamed from HBM (15 N_p^2 words per element, shared by the E and H
+//   waves of an axis);
+// * element-constant coefficients (one sigma_u, kappa_u per element):
+//   the weighted mass matrices are multiples of M_k, so 1 and 5 are
+//   pointwise: w = -(b f + c P), rhs_P = f / kappa - d P, rhs_f = w / a.
 #include "device.hpp"
 
 namespace wdg {
@@ -46,7 +57,7 @@ __device__ __forceinline__ int remap_block(int bid, int nblk_pml, int nblk) {
     return base + x * q + (x < r ? x : r) + i;
 }
 
-template <typename real, int N, bool KAPPA>
+template <typename real, int N, bool KAPPA, int MODE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     constexpr int Np = Ord<N>::Np, Nfp = Ord<N>::Nfp, B = kBlock;
     constexpr int EHS = 6 * Np * B;  // E,H words per block
@@ -76,10 +87,11 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
 
     real w[Np];      // bracket of eqs. (26)-(27), then rhs of f
     real rhsP[Np];   // rhs of the auxiliary field
+    real f[Np], P[Np];  // own field component and its auxiliary field (PML blocks)
+    real ainv = real(1);  // element-constant scheme: 1 / a_uu
 
-    // ---- 1. PML terms from sigma at the cubature points
+    // ---- 1. PML terms
     if (pml) {
-        real f[Np], P[Np];
 #pragma unroll
         for (int j = 0; j < Np; ++j) {
             f[j] = qe[(u * Np + j) * B];
@@ -87,6 +99,25 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
             w[j] = real(0);
             rhsP[j] = real(0);
         }
+    }
+    if (pml && MODE == kPmlConstant) {
+        // eq. (9) at the element's constant sigma, kappa
+        const real* __restrict__ ec = static_cast<const real*>(p.pml_mats) + static_cast<size_t>(blk) * 6 * B + lane;
+        const real sa = ec[ax * B], sb = ec[bb * B], sc = ec[cc * B];
+        const real ka = ec[(3 + ax) * B], kb = ec[(3 + bb) * B], kc = ec[(3 + cc) * B];
+        const real kinv = real(1) / ka;
+        const real a = kb * kc * kinv;
+        const real bq = (sb * kc + sc * kb - a * sa) * kinv;
+        const real cq = sb * sc - bq * sa;
+        const real dq = sa * kinv;
+        ainv = ka / (kb * kc);
+#pragma unroll
+        for (int j = 0; j < Np; ++j) {
+            w[j] = -(bq * f[j] + cq * P[j]);
+            rhsP[j] = kinv * f[j] - dq * P[j];
+        }
+    }
+    if (pml && MODE == kPmlWaa) {
         const real* __restrict__ sg = static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + lane;
         const real* __restrict__ kp =
             KAPPA ? static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + lane : nullptr;
@@ -122,7 +153,8 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
                 rhsP[i] += pw * t2;
             }
         }
-    } else {
+    }
+    if (!pml) {
 #pragma unroll
         for (int i = 0; i < Np; ++i) w[i] = real(0);
     }
@@ -193,7 +225,11 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     }
 
     // ---- 5. weight-adjusted inverse mass: rhs_f = P_q a^{-1} V_q w
-    if (pml) {
+    if (pml && MODE == kPmlConstant) {
+#pragma unroll
+        for (int i = 0; i < Np; ++i) w[i] *= ainv;
+    }
+    if (pml && MODE == kPmlWaa) {
         real rf[Np];
 #pragma unroll
         for (int i = 0; i < Np; ++i) rf[i] = real(0);
@@ -220,6 +256,34 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     const real A = static_cast<real>(p.rk_a), Bk = static_cast<real>(p.rk_b);
     // time step of this lane's element (a per-element scale lets independent simulations share a launch)
     const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + lane] : p.dt);
+    if (MODE == kPmlDirect && pml) {
+        // ---- 5+6, direct scheme: stored per-element products, one output row at a time
+        const real* __restrict__ G = static_cast<const real*>(p.pml_mats) +
+                                     (static_cast<size_t>(blk) * 3 + ax) * kDirectMats * Np * Np * B + lane;
+        constexpr size_t MS = static_cast<size_t>(Np) * Np * B;  // one matrix
+        const size_t eb = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
+        const size_t ebp = pbase + static_cast<size_t>(u) * Np * B;
+        for (int i = 0; i < Np; ++i) {
+            const real* __restrict__ g = G + static_cast<size_t>(i) * Np * B;
+            real rf = real(0), rp = real(0);
+#pragma unroll
+            for (int j = 0; j < Np; ++j) {
+                rf += g[j * B] * w[j] - g[MS + j * B] * f[j] - g[2 * MS + j * B] * P[j];
+                rp += g[3 * MS + j * B] * f[j] - g[4 * MS + j * B] * P[j];
+            }
+            const size_t idx = eb + static_cast<size_t>(i) * B;
+            real r = dt * rf;
+            if (p.read_res) r += A * rs[idx];
+            rs[idx] = r;
+            qo[idx] = qin[idx] + Bk * r;
+            const size_t idp = ebp + static_cast<size_t>(i) * B;
+            real r2 = dt * rp;
+            if (p.read_res) r2 += A * rs[idp];
+            rs[idp] = r2;
+            qo[idp] = qin[idp] + Bk * r2;
+        }
+        return;
+    }
     {
         const size_t eb = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
 #pragma unroll
@@ -299,19 +363,29 @@ __global__ __launch_bounds__(256) void sum_kernel(const double* partial, int n, 
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-template <typename real, int N, bool KAPPA>
+template <typename real, int N, bool KAPPA, int MODE>
 int launch_stage_t(const StageParams& p, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<real, N, KAPPA>), dim3(p.nblk), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL((stage_kernel<real, N, KAPPA, MODE>), dim3(p.nblk), dim3(kThreads), 0, s, p);
     return static_cast<int>(hipGetLastError());
 }
 
+template <typename real, int N>
+int launch_stage_n(bool k, int mode, const StageParams& p, hipStream_t s) {
+    switch (mode) {
+        case kPmlWaa: return k ? launch_stage_t<real, N, true, kPmlWaa>(p, s) : launch_stage_t<real, N, false, kPmlWaa>(p, s);
+        case kPmlDirect: return launch_stage_t<real, N, false, kPmlDirect>(p, s);
+        case kPmlConstant: return launch_stage_t<real, N, false, kPmlConstant>(p, s);
+        default: return static_cast<int>(hipErrorInvalidValue);
+    }
+}
+
 template <typename real>
-int launch_stage_r(int N, bool k, const StageParams& p, hipStream_t s) {
+int launch_stage_r(int N, bool k, int mode, const StageParams& p, hipStream_t s) {
     switch (N) {
-        case 1: return k ? launch_stage_t<real, 1, true>(p, s) : launch_stage_t<real, 1, false>(p, s);
-        case 2: return k ? launch_stage_t<real, 2, true>(p, s) : launch_stage_t<real, 2, false>(p, s);
-        case 3: return k ? launch_stage_t<real, 3, true>(p, s) : launch_stage_t<real, 3, false>(p, s);
-        case 4: return k ? launch_stage_t<real, 4, true>(p, s) : launch_stage_t<real, 4, false>(p, s);
+        case 1: return launch_stage_n<real, 1>(k, mode, p, s);
+        case 2: return launch_stage_n<real, 2>(k, mode, p, s);
+        case 3: return launch_stage_n<real, 3>(k, mode, p, s);
+        case 4: return launch_stage_n<real, 4>(k, mode, p, s);
         default: return static_cast<int>(hipErrorInvalidValue);
     }
 }
@@ -331,8 +405,9 @@ int launch_energy_t(const EnergyParams& p, double* out, hipStream_t s) {
 
 }  // namespace
 
-int launch_stage(int precision, int N, bool has_kappa, const StageParams& p, hipStream_t s) {
-    return precision == 0 ? launch_stage_r<double>(N, has_kappa, p, s) : launch_stage_r<float>(N, has_kappa, p, s);
+int launch_stage(int precision, int N, bool has_kappa, int pml_mode, const StageParams& p, hipStream_t s) {
+    return precision == 0 ? launch_stage_r<double>(N, has_kappa, pml_mode, p, s)
+                          : launch_stage_r<float>(N, has_kappa, pml_mode, p, s);
 }
 
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s) {

@@ -36,6 +36,7 @@ WDG_FP64, WDG_FP32 = 0, 1
 WDG_HOST_ONLY = 1
 WDG_OP_DR, WDG_OP_DS, WDG_OP_DT, WDG_OP_LIFT, WDG_OP_VQ, WDG_OP_PQ, WDG_OP_M = range(7)
 WDG_KERNEL_AUTO, WDG_KERNEL_SCALAR, WDG_KERNEL_MFMA = 0, 1, 2
+WDG_PML_WAA, WDG_PML_DIRECT, WDG_PML_CONSTANT = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -57,7 +58,7 @@ class wdg_dims_t(C.Structure):
                 ("Nfp", C.c_int32), ("Nq", C.c_int32), ("block", C.c_int32), ("nblk_pml", C.c_int32),
                 ("nblk", C.c_int32), ("precision", C.c_int32), ("has_kappa", C.c_int32),
                 ("state_bytes", C.c_int64), ("dt_unit", C.c_double), ("time", C.c_double), ("steps", C.c_int64),
-                ("kernel", C.c_int32), ("tiles", C.c_int32)]
+                ("kernel", C.c_int32), ("tiles", C.c_int32), ("pml_scheme", C.c_int32)]
 
 
 class wdg_dipole(C.Structure):
@@ -68,7 +69,7 @@ class wdg_dipole(C.Structure):
 class wdg_mem_t(C.Structure):
     _fields_ = [("state", C.c_int64), ("geometry", C.c_int64), ("connectivity", C.c_int64),
                 ("coefficients", C.c_int64), ("operators", C.c_int64), ("paper_direct", C.c_int64),
-                ("paper_waa", C.c_int64)]
+                ("paper_waa", C.c_int64), ("scheme_data", C.c_int64)]
 
 
 _ctx = C.c_void_p
@@ -101,6 +102,7 @@ wdg_set_dipole = _sig("wdg_set_dipole", C.c_int32, _ctx, C.POINTER(wdg_dipole))
 wdg_set_probes = _sig("wdg_set_probes", C.c_int32, _ctx, C.c_int32, _dp, C.c_int32)
 wdg_probe_read = _sig("wdg_probe_read", C.c_int32, _ctx, _dp, C.c_int32, _ip)
 wdg_set_kernel = _sig("wdg_set_kernel", C.c_int32, _ctx, C.c_int32)
+wdg_set_pml_scheme = _sig("wdg_set_pml_scheme", C.c_int32, _ctx, C.c_int32, C.c_int32, _dp, _dp)
 wdg_step = _sig("wdg_step", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
 wdg_rhs = _sig("wdg_rhs", C.c_int32, _ctx, C.c_double, C.c_void_p)
 wdg_energy = _sig("wdg_energy", C.c_int32, _ctx, _dp, C.c_void_p)
@@ -317,6 +319,17 @@ class Simulation(Context):
 
     def set_kernel(self, variant):
         _check(wdg_set_kernel(self.h, int(variant)), self.h)
+        self.dims = self.get_dims()
+
+    def set_pml_scheme(self, scheme, rule=None):
+        """WDG_PML_WAA, WDG_PML_DIRECT (rule = (rst [nr, 3], w [nr]) for the weighted mass matrices) or
+        WDG_PML_CONSTANT."""
+        if rule is None:
+            _check(wdg_set_pml_scheme(self.h, int(scheme), 0, None, None), self.h)
+        else:
+            rst, w = _f64(np.asarray(rule[0]).reshape(-1, 3)), _f64(np.asarray(rule[1]).reshape(-1))
+            assert len(rst) == len(w)
+            _check(wdg_set_pml_scheme(self.h, int(scheme), len(w), _ptr(rst), _ptr(w)), self.h)
         self.dims = self.get_dims()
 
     def step(self, dt, nsteps, stream=None):

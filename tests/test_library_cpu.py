@@ -182,3 +182,16 @@ def test_batch_recipe_and_group_profiles():
         assert np.array_equal(ctx.element_info()["is_pml"][offs[g]:offs[g + 1]], alone.element_info()["is_pml"])
     with pytest.raises(wdg.WdgError):
         ctx.set_sigma_profile(group, [[1.0] * 3], [2.0])  # group index out of range
+
+
+def test_pml_scheme_errors_on_host_only_context(rules):
+    cfg = inputs.config("c1")
+    vx, ev = inputs.mesh_for(cfg)
+    ctx = wdg.Context(vx, ev, cfg["N"], rules(cfg["cub_degree"]), cfg["pml"], host_only=True)
+    # the scheme call lives on Simulation (it needs a device); call the ABI directly
+    with pytest.raises(wdg.WdgError) as e:
+        wdg._check(wdg.wdg_set_pml_scheme(ctx.h, 9, 0, None, None), ctx.h)
+    assert e.value.code == wdg.WDG_EINVAL
+    with pytest.raises(wdg.WdgError) as e:
+        wdg._check(wdg.wdg_set_pml_scheme(ctx.h, wdg.WDG_PML_CONSTANT, 0, None, None), ctx.h)
+    assert e.value.code == wdg.WDG_ESTATE

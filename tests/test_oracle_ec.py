@@ -98,3 +98,27 @@ def test_ec_without_conductivity_is_vacuum(rules):
     r1, r0 = ec.rhs(q, 0.0), vac.rhs(q, 0.0)
     assert np.max(np.abs(r1[:, :6] - r0[:, :6])) < 1e-12 * np.max(np.abs(r0))
     assert np.array_equal(r1[ec.pml_elems, 6:], q[ec.pml_elems, :6])  # dP = f when kappa = 1, d = 0
+
+
+def test_direct_oracle_with_the_product_rule_input(rules):
+    # the stored-matrix oracle fed the input product rule agrees with its own rule of the same degree on
+    # elements whose weights are polynomial (an aligned slab with a linear profile: both rules are exact),
+    # and the element subset gives the same rows as the full operator
+    N = 2
+    ref = RefElement(N, *rules(2 * N))
+    vx, ev = inputs.kuhn_box(4, -1.0, 1.0, 0.0, seed=0)
+    mesh = Mesh(vx, ev, ref)
+    pml = {"lo": [-9.0, -9.0, -0.5], "hi": [9.0, 9.0, 0.5], "L": [1.0, 1.0, 0.5], "sigma_max": [0.0, 0.0, 6.0],
+           "order": 1.0, "kappa_max": 1.0}
+    a = BruteOperator(mesh, ref, pml, quad_points=6)
+    b = BruteOperator(mesh, ref, pml, rule=inputs.product_rule(6))
+    rng = np.random.default_rng(8)
+    q = rng.standard_normal((mesh.K, 12, ref.Np))
+    q[~a.is_pml, 6:] = 0.0
+    ra, rb = a.rhs(q, 0.0), b.rhs(q, 0.0)
+    assert np.max(np.abs(ra - rb)) < 1e-12 * np.max(np.abs(ra))
+    el = a.pml_elems[::7]
+    c = BruteOperator(mesh, ref, pml, rule=inputs.product_rule(6), elements=el)
+    assert np.max(np.abs(c.rhs(q, 0.0, el=el) - rb[el])) < 1e-14 * np.max(np.abs(ra))
+    with pytest.raises(ValueError):
+        c.rhs(q, 0.0, el=a.pml_elems[1:2])
