@@ -12,11 +12,13 @@ inverse mass and the Runge-Kutta update) plus the probe readout.  Fields live
 in HBM before the timed region starts.  The metric is
 K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
 
-Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`) and the
-batching form's throughput (`batch`: 32 independent simulations in one context).
+Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`), the
+batching form's throughput (`batch`: 32 independent simulations in one context) and the Table I contrast
+(`table_i`: memory and time per step of the weight-adjusted, direct stored-matrix and element-constant
+PML schemes, N = 1..4).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--stepping-only]
-                       [--copy-calibration MIB]
+                       [--table-i-only] [--copy-calibration MIB]
 """
 from __future__ import annotations
 
@@ -216,6 +218,67 @@ def run_batch(steps, warmup, seq_steps=50):
                         "sequential = each simulation in its own context, eager steps, one after another"}
 
 
+def run_table_i(steps=40, warmup=3):
+    """The Table I contrast on the GPU: memory and time per step of the weight-adjusted scheme against the
+    direct scheme with stored per-element matrices (and element-constant coefficients), N = 1..4, FP64, on
+    the 73,002-tet stand-in of Table I's mesh."""
+    import torch
+
+    from paper_2006_02551_amd import inputs, wdg
+
+    rows = []
+    stream = torch.cuda.current_stream()
+    for N in (1, 2, 3, 4):
+        cfg = inputs.config("t1", N=N, cub_degree=2 * N)
+        vx, ev = inputs.mesh_for(cfg)
+        sim = wdg.Simulation(vx, ev, N, inputs.load_rule(2 * N), cfg["pml"], cfg["alpha"], wdg.WDG_FP64)
+        d = sim.dims
+        q0 = inputs.gaussian_fields(cfg, sim.node_coords())
+        dt = cfg["cfl"] * d.dt_unit
+
+        def timed():
+            sim.set_fields(q0)
+            sim.step(dt, warmup, stream)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sim.step(dt, steps, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            assert abs(sim.energy()) < 1e30
+            return a.elapsed_time(b) / steps
+
+        mem = sim.memory_report()
+        common = mem["state"] + mem["geometry"] + mem["connectivity"] + mem["operators"]
+        row = {"N": N, "Np": d.Np, "Nq": d.Nq, "K": d.K, "K_pml": d.K_pml}
+        t = {"waa": timed(), "waa_kernel": "mfma" if sim.dims.kernel == wdg.WDG_KERNEL_MFMA else "scalar"}
+        sim.set_kernel(wdg.WDG_KERNEL_SCALAR)
+        t["waa_scalar"] = timed()
+        t0 = time.perf_counter()
+        sim.set_pml_scheme(wdg.WDG_PML_DIRECT, inputs.product_rule(N + 4))
+        row["direct_setup_s"] = time.perf_counter() - t0
+        direct_bytes = sim.memory_report()["scheme_data"]
+        t["direct"] = timed()
+        sim.set_pml_scheme(wdg.WDG_PML_CONSTANT)
+        t["element_constant"] = timed()
+        row["ms_per_step"] = t
+        row["memory_MB"] = {"waa_total": (common + mem["coefficients"]) / 1e6,
+                            "direct_total": (common + direct_bytes) / 1e6,
+                            "waa_pml_data": mem["coefficients"] / 1e6, "direct_pml_data": direct_bytes / 1e6,
+                            "paper_model_waa": mem["paper_waa"] / 1e6, "paper_model_direct": mem["paper_direct"] / 1e6}
+        row["direct_over_waa"] = {"memory": row["memory_MB"]["direct_total"] / row["memory_MB"]["waa_total"],
+                                  "time": t["direct"] / t["waa"]}
+        print(f"bench: table I N={N}: WAA {t['waa']:.3f} ms/step ({t['waa_kernel']}), direct {t['direct']:.3f}, "
+              f"element-constant {t['element_constant']:.3f}; memory {row['memory_MB']['waa_total']:.0f} vs "
+              f"{row['memory_MB']['direct_total']:.0f} MB", file=sys.stderr, flush=True)
+        rows.append(row)
+        del sim
+    return {"workload": "t1: 23^3x6 = 73,002 perturbed tets, 52,752 in the PML (Table I: 72,762 / 52,657), cubic "
+                        "profile sigma_max = 30, cubature of degree 2N, FP64, Gaussian Ez pulse; direct matrices "
+                        "integrated with the conical product rule of (N+4)^3 points",
+            "steps": steps, "rows": rows}
+
+
 def cpu_baseline(cfg, steps=3):
     """The FP64 oracle on the host cores for a bounded sample (three LSERK4 steps, about 15 s)."""
     import numpy as np
@@ -245,6 +308,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stepping-only", action="store_true",
                     help="run the c2 stepping legs only (no adjoint or batch legs), e.g. under a profiler")
+    ap.add_argument("--table-i-only", action="store_true",
+                    help="run the Table I contrast only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (a known-size reference for "
                          "hardware traffic counters)")
@@ -268,6 +333,9 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: copied {args.copy_calibration} MiB three times", file=sys.stderr, flush=True)
         del src, dst
+    if args.table_i_only:
+        print(json.dumps({"table_i": run_table_i()}))
+        return
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
     r64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup)
@@ -275,7 +343,7 @@ def main():
           file=sys.stderr, flush=True)
     r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup)
     print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    adj64 = adj32 = batch = None
+    adj64 = adj32 = batch = table_i = None
     if not args.stepping_only:
         print("bench: adjoint (loss gradient) against plain stepping, 500 steps, FP64 and FP32", file=sys.stderr,
               flush=True)
@@ -284,8 +352,9 @@ def main():
         print(f"bench: adjoint/forward {adj64['ratio']:.2f} (FP64), {adj32['ratio']:.2f} (FP32); batch next",
               file=sys.stderr, flush=True)
         batch = run_batch(max(args.steps // 5, 20), 4)
-        print(f"bench: batch {batch['value']:.3e} DOF/s ({batch['speedup_vs_sequential']:.2f}x sequential)",
-              file=sys.stderr, flush=True)
+        print(f"bench: batch {batch['value']:.3e} DOF/s ({batch['speedup_vs_sequential']:.2f}x sequential); "
+              f"Table I contrast next", file=sys.stderr, flush=True)
+        table_i = run_table_i()
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on three steps", file=sys.stderr, flush=True)
@@ -328,6 +397,7 @@ def main():
             "fp64": {k: v for k, v in adj64.items() if k != "ratio"},
             "fp32_detail": {k: v for k, v in adj32.items() if k != "ratio"}},
         "batch": batch,
+        "table_i": table_i,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -226,6 +226,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.frags = c->frags.p;
     p.dt_scale = c->has_dt_scale ? static_cast<const double*>(c->dt_scale.p) : nullptr;
     p.pml_mats = c->pml_mats.p;
+    p.pml_work = c->pml_work.p;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;
@@ -633,7 +634,7 @@ int32_t wdg_memory_report(const wdg_ctx* c, wdg_mem_t* o) {
     o->operators = (3 * Np * Np + Np * 4 * S.ref.Nfp + 2 * Np * Nq) * r;
     o->paper_direct = 15 * Np * Np * static_cast<int64_t>(S.K_pml) * 8;
     o->paper_waa = (15 * Nq * static_cast<int64_t>(S.K_pml) + 2 * Np * Nq) * 8;
-    o->scheme_data = static_cast<int64_t>(c->pml_mats.bytes);
+    o->scheme_data = static_cast<int64_t>(c->pml_mats.bytes + c->pml_work.bytes);
     return WDG_OK;
 }
 

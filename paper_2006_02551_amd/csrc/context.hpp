@@ -85,7 +85,7 @@ struct wdg_ctx {
     // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored
     // matrices or the element-constant coefficients (empty for the weight-adjusted scheme)
     int pml_scheme = WDG_PML_WAA;
-    wdg::DevBuf pml_mats;
+    wdg::DevBuf pml_mats, pml_work;
     bool sigma_custom = false;  // sigma at the cubature points no longer follows the method's profile
     // per-element factor on dt (independent simulations sharing one launch)
     wdg::DevBuf dt_scale;

@@ -76,6 +76,7 @@ struct StageParams {
     const double* Jk;     // [nblk][B] Jacobians
     const double* dt_scale;  // [nblk][B] per-element factor on dt, or null (uniform dt)
     const void* pml_mats;    // direct matrices or element-constant coefficients (see the layout above)
+    void* pml_work;          // direct scheme: [nblk_pml][6][Np][B] vacuum right-hand side of the PML blocks
     int nblk_pml, nblk, Nq;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;

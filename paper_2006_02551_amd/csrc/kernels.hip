@@ -23,11 +23,11 @@
 //
 // The same kernel evaluates two other PML schemes for comparison:
 // * direct (stored matrices, eqs. (10)-(15) with exact weighted mass
-//   matrices): 1 only loads f and P; 5 becomes, row by row,
-//     rhs_f = G_1 w - G_2 f - G_3 P,   rhs_P = G_4 f - G_5 P
-//   with the five per-element N_p x N_p products of the layout in device.hpp,
-//   streamed from HBM (15 N_p^2 words per element, shared by the E and H
-//   waves of an axis);
+//   matrices): on PML blocks this kernel stops after 4 and writes w (the
+//   vacuum right-hand side) to a work buffer; direct_apply_kernel then
+//   streams the five per-element N_p x N_p products of the layout in
+//   device.hpp (15 N_p^2 words per element) and finishes 5 and 6:
+//     rhs_f = G_1 w - G_2 f - G_3 P,   rhs_P = G_4 f - G_5 P;
 // * element-constant coefficients (one sigma_u, kappa_u per element):
 //   the weighted mass matrices are multiples of M_k, so 1 and 5 are
 //   pointwise: w = -(b f + c P), rhs_P = f / kappa - d P, rhs_f = w / a.
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     real ainv = real(1);  // element-constant scheme: 1 / a_uu
 
     // ---- 1. PML terms
-    if (pml) {
+    if (pml && MODE != kPmlDirect) {
 #pragma unroll
         for (int j = 0; j < Np; ++j) {
             f[j] = qe[(u * Np + j) * B];
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
             }
         }
     }
-    if (!pml) {
+    if (!pml || MODE == kPmlDirect) {
 #pragma unroll
         for (int i = 0; i < Np; ++i) w[i] = real(0);
     }
@@ -224,6 +224,14 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
         }
     }
 
+    if (MODE == kPmlDirect && pml) {
+        // the direct scheme's PML terms and update follow in direct_apply_kernel
+        real* __restrict__ wo = static_cast<real*>(p.pml_work) + (static_cast<size_t>(blk) * 6 + u) * Np * B + lane;
+#pragma unroll
+        for (int i = 0; i < Np; ++i) wo[i * B] = w[i];
+        return;
+    }
+
     // ---- 5. weight-adjusted inverse mass: rhs_f = P_q a^{-1} V_q w
     if (pml && MODE == kPmlConstant) {
 #pragma unroll
@@ -256,34 +264,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     const real A = static_cast<real>(p.rk_a), Bk = static_cast<real>(p.rk_b);
     // time step of this lane's element (a per-element scale lets independent simulations share a launch)
     const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + lane] : p.dt);
-    if (MODE == kPmlDirect && pml) {
-        // ---- 5+6, direct scheme: stored per-element products, one output row at a time
-        const real* __restrict__ G = static_cast<const real*>(p.pml_mats) +
-                                     (static_cast<size_t>(blk) * 3 + ax) * kDirectMats * Np * Np * B + lane;
-        constexpr size_t MS = static_cast<size_t>(Np) * Np * B;  // one matrix
-        const size_t eb = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
-        const size_t ebp = pbase + static_cast<size_t>(u) * Np * B;
-        for (int i = 0; i < Np; ++i) {
-            const real* __restrict__ g = G + static_cast<size_t>(i) * Np * B;
-            real rf = real(0), rp = real(0);
-#pragma unroll
-            for (int j = 0; j < Np; ++j) {
-                rf += g[j * B] * w[j] - g[MS + j * B] * f[j] - g[2 * MS + j * B] * P[j];
-                rp += g[3 * MS + j * B] * f[j] - g[4 * MS + j * B] * P[j];
-            }
-            const size_t idx = eb + static_cast<size_t>(i) * B;
-            real r = dt * rf;
-            if (p.read_res) r += A * rs[idx];
-            rs[idx] = r;
-            qo[idx] = qin[idx] + Bk * r;
-            const size_t idp = ebp + static_cast<size_t>(i) * B;
-            real r2 = dt * rp;
-            if (p.read_res) r2 += A * rs[idp];
-            rs[idp] = r2;
-            qo[idp] = qin[idp] + Bk * r2;
-        }
-        return;
-    }
     {
         const size_t eb = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
 #pragma unroll
@@ -304,6 +284,78 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
             if (p.read_res) r += A * rs[idx];
             rs[idx] = r;
             qo[idx] = qin[idx] + Bk * r;
+        }
+    }
+}
+
+// Direct scheme, PML terms and Runge-Kutta update of one (PML block, axis u):
+// the six vectors E_u, H_u, P^E_u, P^H_u, w_E, w_H of the block's 64 elements
+// are staged in LDS; wave v then takes output rows i = v, v + W, ... and, per
+// row, reads the five stored rows G_m[i][:] once (64-lane coalesced) for both
+// fields, so every matrix word crosses HBM once per stage.
+constexpr int kApplyWaves = 8;
+
+template <typename real, int N>
+__global__ __launch_bounds__(kApplyWaves * 64) void direct_apply_kernel(StageParams p) {
+    constexpr int Np = Ord<N>::Np, B = kBlock;
+    constexpr int EHS = 6 * Np * B;
+    constexpr size_t MS = static_cast<size_t>(Np) * Np * B;  // one stored matrix
+    __shared__ real xs[6][Np][B];  // E_u, H_u, PE_u, PH_u, w_E, w_H
+
+    const int blk = blockIdx.x / 3, ax = blockIdx.x % 3;
+    const int tid = static_cast<int>(threadIdx.x);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    const real* __restrict__ qin = static_cast<const real*>(p.q_in);
+    const real* __restrict__ wk = static_cast<const real*>(p.pml_work);
+    const size_t eh = static_cast<size_t>(blk) * EHS;                                 // E,H part of the block
+    const size_t ph = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS;  // auxiliary part
+    for (int e = tid; e < 6 * Np * B; e += kApplyWaves * 64) {
+        const int v = e / (Np * B), r = e % (Np * B);
+        size_t src;
+        const real* base = qin;
+        switch (v) {
+            case 0: src = eh + static_cast<size_t>(ax) * Np * B; break;
+            case 1: src = eh + static_cast<size_t>(3 + ax) * Np * B; break;
+            case 2: src = ph + static_cast<size_t>(ax) * Np * B; break;
+            case 3: src = ph + static_cast<size_t>(3 + ax) * Np * B; break;
+            case 4: src = (static_cast<size_t>(blk) * 6 + ax) * Np * B; base = wk; break;
+            default: src = (static_cast<size_t>(blk) * 6 + 3 + ax) * Np * B; base = wk; break;
+        }
+        (&xs[v][0][0])[r] = base[src + r];
+    }
+    __syncthreads();
+
+    const real* __restrict__ G =
+        static_cast<const real*>(p.pml_mats) + (static_cast<size_t>(blk) * 3 + ax) * kDirectMats * MS + lane;
+    real* __restrict__ rs = static_cast<real*>(p.res);
+    real* __restrict__ qo = static_cast<real*>(p.q_out);
+    const real A = static_cast<real>(p.rk_a), Bk = static_cast<real>(p.rk_b);
+    const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + lane] : p.dt);
+    for (int i = wave; i < Np; i += kApplyWaves) {
+        const real* __restrict__ g = G + static_cast<size_t>(i) * Np * B;
+        real fE = real(0), fH = real(0), pE = real(0), pH = real(0);
+        // a partial unroll keeps 20 row loads in flight per wave at a modest register count
+#pragma unroll 4
+        for (int j = 0; j < Np; ++j) {
+            const real g1 = g[j * B], g2 = g[MS + j * B], g3 = g[2 * MS + j * B];
+            const real g4 = g[3 * MS + j * B], g5 = g[4 * MS + j * B];
+            const real e = xs[0][j][lane], h = xs[1][j][lane], pe = xs[2][j][lane], phv = xs[3][j][lane];
+            fE += g1 * xs[4][j][lane] - g2 * e - g3 * pe;
+            fH += g1 * xs[5][j][lane] - g2 * h - g3 * phv;
+            pE += g4 * e - g5 * pe;
+            pH += g4 * h - g5 * phv;
+        }
+        const real out[4] = {fE, fH, pE, pH};
+        const size_t idx[4] = {eh + (static_cast<size_t>(ax) * Np + i) * B + lane,
+                               eh + (static_cast<size_t>(3 + ax) * Np + i) * B + lane,
+                               ph + (static_cast<size_t>(ax) * Np + i) * B + lane,
+                               ph + (static_cast<size_t>(3 + ax) * Np + i) * B + lane};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            real r = dt * out[c];
+            if (p.read_res) r += A * rs[idx[c]];
+            rs[idx[c]] = r;
+            qo[idx[c]] = xs[c][i][lane] + Bk * r;
         }
     }
 }
@@ -370,10 +422,18 @@ int launch_stage_t(const StageParams& p, hipStream_t s) {
 }
 
 template <typename real, int N>
+int launch_direct(const StageParams& p, hipStream_t s) {
+    const int e = launch_stage_t<real, N, false, kPmlDirect>(p, s);
+    if (e != 0 || p.nblk_pml == 0) return e;
+    hipLaunchKernelGGL((direct_apply_kernel<real, N>), dim3(3 * p.nblk_pml), dim3(kApplyWaves * 64), 0, s, p);
+    return static_cast<int>(hipGetLastError());
+}
+
+template <typename real, int N>
 int launch_stage_n(bool k, int mode, const StageParams& p, hipStream_t s) {
     switch (mode) {
         case kPmlWaa: return k ? launch_stage_t<real, N, true, kPmlWaa>(p, s) : launch_stage_t<real, N, false, kPmlWaa>(p, s);
-        case kPmlDirect: return launch_stage_t<real, N, false, kPmlDirect>(p, s);
+        case kPmlDirect: return launch_direct<real, N>(p, s);
         case kPmlConstant: return launch_stage_t<real, N, false, kPmlConstant>(p, s);
         default: return static_cast<int>(hipErrorInvalidValue);
     }

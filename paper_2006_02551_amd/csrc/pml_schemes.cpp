@@ -143,6 +143,7 @@ int build_direct(wdg_ctx* c, int nr, const double* rst, const double* w) {
     const size_t blk_words = 3 * kDirectMats * NN * B;
     const size_t rs = c->rsize;
     c->pml_mats.alloc(static_cast<size_t>(S.nblk_pml) * blk_words * rs);
+    c->pml_work.alloc(static_cast<size_t>(S.nblk_pml) * 6 * Np * B * rs);
     if (S.nblk_pml == 0) return WDG_OK;
 
     const int nthreads = std::max(1, std::min(16, static_cast<int>(std::thread::hardware_concurrency())));
@@ -243,12 +244,14 @@ int32_t wdg_set_pml_scheme(wdg_ctx* c, int32_t scheme, int32_t nr, const double*
     return guarded(c, [&]() -> int {
         c->drop_graph();
         c->pml_mats.alloc(0);
+        c->pml_work.alloc(0);
         c->pml_scheme = WDG_PML_WAA;
         int rc = WDG_OK;
         if (scheme == WDG_PML_DIRECT) rc = build_direct(c, nr, rst, w);
         else if (scheme == WDG_PML_CONSTANT) rc = build_constant(c);
         if (rc != WDG_OK) {
             c->pml_mats.alloc(0);
+            c->pml_work.alloc(0);
             return rc;
         }
         c->pml_scheme = scheme;

@@ -73,6 +73,14 @@ CONFIGS = {
            "alpha": 1.0, "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.25},
            "source": None, "probes": None, "steps": 500, "cfl": CFL,
            "batch": {"nsim": 32, "n_range": [8, 24], "sigma_range": [10.0, 50.0], "orders": [2, 3, 4], "seed": 0}},
+    # Table I stand-in: 23^3 x 6 = 73,002 perturbed tets (52,752 in the PML, 72.3%; Table I: 72,762 and
+    # 52,657), the c2 box and cubic profile; the order N is scanned 1..4 with cubature of degree 2N.
+    "t1": {"name": "t1", "N": 3, "cub_degree": 6,
+           "mesh": {"n": 23, "lo": -1.5, "hi": 1.5, "perturb": 0.1, "seed": 0},
+           "pml": {"lo": [-1.0] * 3, "hi": [1.0] * 3, "L": [0.5] * 3, "sigma_max": [30.0] * 3,
+                   "order": 3.0, "kappa_max": 1.0},
+           "alpha": 1.0, "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.25},
+           "source": None, "probes": None, "steps": 50, "cfl": CFL},
     # Differentiation form: the 48,000-tet N=3 mesh and cubic profile of c2, a Gaussian Ez pulse at the
     # origin that reaches the layer within the 500 steps, loss = time-integrated energy in the shell
     # 0.1 inside the PML interface.

@@ -120,7 +120,8 @@ def test_scheme_data_switching_and_errors(wdg):
     sim, vx, ev, rule = _ctx(wdg, cfg, 0, wdg.WDG_PML_DIRECT)
     d = sim.dims
     mem = sim.memory_report()
-    assert mem["scheme_data"] == d.nblk_pml * d.block * 15 * d.Np * d.Np * 8
+    # stored products plus the work buffer of the vacuum right-hand side (6 N_p words per PML slot)
+    assert mem["scheme_data"] == d.nblk_pml * d.block * (15 * d.Np * d.Np + 6 * d.Np) * 8
     assert mem["paper_direct"] == 15 * d.Np * d.Np * d.K_pml * 8
     # captured stepping follows the scheme
     q = inputs.gaussian_fields(cfg, sim.node_coords())
