@@ -14,8 +14,13 @@ Construction used here:
   physical face edges, flipped to point away from the opposite vertex; the
   surface Jacobian is sJ = (face area)/2 and Fscale = sJ / J_k;
 * faces are matched through their sorted global vertex triples; face nodes
-  are matched by physical coordinates; a face with no partner is a perfect
-  electric conductor (PEC) wall.
+  are matched by physical coordinates relative to the face centroid; a face
+  with no partner is a perfect electric conductor (PEC) wall;
+* periodic meshes: an optional vertex identification vertex_id [nv] names, for
+  every vertex, the vertex it stands for; faces are matched on identified
+  triples, so a face on the upper side of a periodic box meets its image on
+  the lower side (its nodes differ by the period, which the centroid-relative
+  node matching ignores).
 
 Negatively oriented input tetrahedra have their last two vertices swapped.
 
@@ -32,9 +37,10 @@ OPPOSITE = (3, 2, 0, 1)  # local vertex not on face f
 
 
 class Mesh:
-    def __init__(self, vxyz: np.ndarray, etov: np.ndarray, ref: RefElement):
+    def __init__(self, vxyz: np.ndarray, etov: np.ndarray, ref: RefElement, vertex_id=None):
         vxyz = np.asarray(vxyz, dtype=np.float64)
         etov = np.array(etov, dtype=np.int64, copy=True)
+        self.vertex_id = np.arange(len(vxyz)) if vertex_id is None else np.asarray(vertex_id, dtype=np.int64)
         K = etov.shape[0]
         if K == 0:
             raise ValueError("empty mesh")
@@ -90,9 +96,12 @@ class Mesh:
         faces = {}
         self.EToE = np.tile(np.arange(K)[:, None], (1, 4))
         self.EToF = np.tile(np.arange(4)[None, :], (K, 1))
+        ids = self.vertex_id[self.etov]
+        if np.any([len(set(row)) < 4 for row in ids]):
+            raise ValueError("the vertex identification collapses an element")
         for k in range(K):
             for f, tri in enumerate(FACE_VERTS):
-                key = tuple(sorted(self.etov[k, list(tri)]))
+                key = tuple(sorted(ids[k, list(tri)]))
                 faces.setdefault(key, []).append((k, f))
         for key, lst in faces.items():
             if len(lst) > 2:
@@ -117,6 +126,8 @@ class Mesh:
                 k2, f2 = self.EToE[k, f], self.EToF[k, f]
                 xm = self.x[k, fm[f]]
                 xp = self.x[k2, fm[f2]]
+                xm = xm - xm.mean(axis=0)
+                xp = xp - xp.mean(axis=0)
                 d = np.linalg.norm(xm[:, None, :] - xp[None, :, :], axis=2)
                 idx = np.argmin(d, axis=1)
                 if np.max(d[np.arange(Nfp), idx]) > tol:

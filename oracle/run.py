@@ -19,14 +19,14 @@ from .rhs import Operator
 
 class Simulation:
     def __init__(self, cfg: dict, vxyz, etov, rst, w, brute: bool = False, sigma_q=None, scheme: str = "waa",
-                 brute_points: int = 9):
+                 brute_points: int = 9, vertex_id=None, brute_rule=None):
         self.cfg = cfg
         self.ref = RefElement(cfg["N"], rst, w)
-        self.mesh = Mesh(vxyz, etov, self.ref)
+        self.mesh = Mesh(vxyz, etov, self.ref, vertex_id=vertex_id)
         scheme = "direct" if brute else scheme
         if scheme == "direct":
             self.op = BruteOperator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"),
-                                    quad_points=brute_points)
+                                    quad_points=brute_points, rule=brute_rule)
         elif scheme == "ec":
             self.op = ECOperator(self.mesh, self.ref, cfg["pml"], cfg["alpha"], cfg.get("source"))
         else:

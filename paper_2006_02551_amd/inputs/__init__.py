@@ -8,5 +8,5 @@ source and probe parameters).  Everything the DG/PML method computes from these
 inputs lives either in the HIP library or, independently, in the oracle.
 """
 from .configs import CONFIGS, config, gaussian_fields, load_rule, mesh_for, product_rule  # noqa: F401
-from .mesh import kuhn_box, orient_positive  # noqa: F401
+from .mesh import kuhn_box, kuhn_grid, orient_positive  # noqa: F401
 from .batch import batch_meshes, batch_recipe, concat_meshes  # noqa: F401
