@@ -59,12 +59,19 @@ extern "C" {
 
 typedef struct wdg_ctx wdg_ctx;
 
-/* Tetrahedral mesh.  vxyz: double [nv][3]; etov: int32 [K][4] (0-based). */
+/* Tetrahedral mesh.  vxyz: double [nv][3]; etov: int32 [K][4] (0-based).
+ * vertex_id: NULL, or int32 [nv] naming for every vertex the vertex it stands
+ * for in the face connectivity (periodic meshes: a vertex on the upper face of a
+ * periodic box identified with its image on the lower face).  Faces are matched
+ * on identified vertex triples; geometry uses the coordinates as given.  A face
+ * with no partner is a PEC wall.  The identification must keep the four vertices
+ * of every element distinct (WDG_EMESH otherwise). */
 typedef struct wdg_mesh {
     int32_t nv;
     const double* vxyz;
     int32_t K;
     const int32_t* etov;
+    const int32_t* vertex_id;
 } wdg_mesh;
 
 /* Discretisation and PML parameters.

@@ -299,8 +299,8 @@ int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* m, wdg_ctx** out) {
         }
         pp.order = m->profile_order;
         pp.kappa_max = m->kappa_max;
-        ctx->S = build_setup(mesh->nv, mesh->vxyz, mesh->K, mesh->etov, m->N, m->nq, m->cub_rst, m->cub_w, pp,
-                             m->flux_alpha);
+        ctx->S = build_setup(mesh->nv, mesh->vxyz, mesh->K, mesh->etov, mesh->vertex_id, m->N, m->nq, m->cub_rst,
+                             m->cub_w, pp, m->flux_alpha);
         ctx->precision = m->precision;
         ctx->rsize = m->precision == WDG_FP64 ? sizeof(double) : sizeof(float);
         ctx->host_only = (m->flags & WDG_HOST_ONLY) != 0;

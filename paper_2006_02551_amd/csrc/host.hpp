@@ -80,7 +80,8 @@ struct Setup {
     double dt_unit = 0.0;
 };
 
-Setup build_setup(int nv, const double* vxyz, int K, const int* etov, int N, int nq,
+// vertex_id: null, or [nv] identification used by the face connectivity (periodic meshes).
+Setup build_setup(int nv, const double* vxyz, int K, const int* etov, const int* vertex_id, int N, int nq,
                   const double* rst, const double* w, const PmlParams& pml, double flux_alpha);
 
 // Element containing a point (largest smallest barycentric coordinate, lowest

@@ -15,7 +15,9 @@
 //    faces t=-1, s=-1, r+s+t=-1, r=-1; Fscale is their length and sJ = Fscale J;
 //  * faces are matched by sorting their vertex triples; face nodes are matched
 //    exactly through their integer barycentric weights on the shared global
-//    vertices, so no coordinate tolerance is involved;
+//    vertices, so no coordinate tolerance is involved; an optional vertex
+//    identification replaces the vertex numbers in both (periodic meshes: the
+//    faces and nodes of a periodic pair meet on identified vertices);
 //  * PML elements come first, then interior elements; inside each class the
 //    elements are grouped by face-connected component (numbered in order of
 //    their lowest element index), ordered along a Morton curve of their
@@ -59,9 +61,13 @@ double profile_ratio(double x, double lo, double hi, double L, double p) {
     return std::pow(d / L, p);
 }
 
-Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, int nq, const double* rst,
-                  const double* w, const PmlParams& pml, double flux_alpha) {
+Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const int* vertex_id, int N, int nq,
+                  const double* rst, const double* w, const PmlParams& pml, double flux_alpha) {
     if (K <= 0 || nv <= 0 || !vxyz || !etov_in) throw Error(-2, "empty mesh");
+    if (vertex_id)
+        for (int i = 0; i < nv; ++i)
+            if (vertex_id[i] < 0 || vertex_id[i] >= nv) throw Error(-2, "vertex identification out of range");
+    auto vid = [&](int v) { return vertex_id ? vertex_id[v] : v; };
     Setup S;
     S.ref = build_reference(N, nq, rst, w);
     const RefElement& R = S.ref;
@@ -142,7 +148,13 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
     }
     S.dt_unit = 1.0 / ((N + 1.0) * (N + 1.0) * fsmax);
 
-    // ---- face matching by sorted vertex triples
+    // ---- face matching by sorted (identified) vertex triples
+    for (int k = 0; k < K; ++k) {
+        const int* ev = &S.etov[4 * static_cast<size_t>(k)];
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j)
+                if (vid(ev[i]) == vid(ev[j])) throw Error(-2, "the vertex identification collapses an element");
+    }
     struct FaceRec {
         std::array<int, 3> key;
         int k, f;
@@ -152,7 +164,7 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
     for (int k = 0; k < K; ++k)
         for (int f = 0; f < 4; ++f) {
             std::array<int, 3> key;
-            for (int i = 0; i < 3; ++i) key[i] = S.etov[4 * static_cast<size_t>(k) + kFaceVerts[f][i]];
+            for (int i = 0; i < 3; ++i) key[i] = vid(S.etov[4 * static_cast<size_t>(k) + kFaceVerts[f][i]]);
             std::sort(key.begin(), key.end());
             faces.push_back({key, k, f});
         }
@@ -198,7 +210,7 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, int N, 
         std::array<std::pair<int, int>, 4> kv;
         int n = 0;
         for (int v = 0; v < 4; ++v)
-            if (lam[node][v] != 0) kv[n++] = {S.etov[4 * static_cast<size_t>(k) + v], lam[node][v]};
+            if (lam[node][v] != 0) kv[n++] = {vid(S.etov[4 * static_cast<size_t>(k) + v]), lam[node][v]};
         std::sort(kv.begin(), kv.begin() + n);
         std::array<int, 8> key;
         key.fill(-1);

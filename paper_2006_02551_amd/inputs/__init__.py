@@ -7,6 +7,7 @@ defines the workload recipes (mesh size, order, absorbing-layer profile,
 source and probe parameters).  Everything the DG/PML method computes from these
 inputs lives either in the HIP library or, independently, in the oracle.
 """
-from .configs import CONFIGS, config, gaussian_fields, load_rule, mesh_for, product_rule  # noqa: F401
+from .configs import (CONFIGS, column_for, config, gaussian_fields, load_rule, mesh_for, plane_pulse_fields,  # noqa: F401
+                      product_rule)
 from .mesh import kuhn_box, kuhn_grid, orient_positive  # noqa: F401
 from .batch import batch_meshes, batch_recipe, concat_meshes  # noqa: F401

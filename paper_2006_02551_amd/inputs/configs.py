@@ -22,6 +22,8 @@ Each recipe is a plain dict:
   shell       (differentiation form) box shell of the loss: outer_lo/hi, inner_lo/hi
   batch       (batching form) nsim, n_range, sigma_range, orders, seed of the per-simulation draws;
               the recipe's mesh box, PML box and thickness are shared
+  column      (reflection study) Kuhn grid n[3], lo[3], hi[3], perturb, seed, periodic[3]
+  plane_pulse (reflection study) right-going Gaussian plane pulse E_x = H_y = exp(-((z-z0)/width)^2)
   cfl         dt = cfl / ((N+1)^2 * max_{k,f} Fscale_{k,f})
 """
 from __future__ import annotations
@@ -31,7 +33,7 @@ import os
 
 import numpy as np
 
-from .mesh import kuhn_box
+from .mesh import kuhn_box, kuhn_grid
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 RULE_DIR = os.path.join(HERE, "cubature")
@@ -81,6 +83,20 @@ CONFIGS = {
                    "order": 3.0, "kappa_max": 1.0},
            "alpha": 1.0, "init": {"component": 2, "center": [0.0, 0.0, 0.0], "width": 0.25},
            "source": None, "probes": None, "steps": 50, "cfl": CFL},
+    # Plane-wave reflection study (normal incidence, Sec. III, Fig. 2): a column periodic in x and y,
+    # 3 x 3 x 60 cubes x 6 = 3,240 tets of edge 0.1 over [0, 0.3]^2 x [0, 6] with interior vertices
+    # perturbed by up to 20% of h (element faces do not follow the layer: a "paved" mesh), PML slabs
+    # z < 1 and z > 5 of thickness 1 ended by PEC walls, quadratic profile; a right-going Gaussian plane
+    # pulse E_x = H_y centred at z = 2 is the initial state, E_x is recorded at z = 3 until t = 8 (the
+    # incident pulse passes at t = 1, the interface reflection returns at t = 5, the wall's at t = 7).
+    "x1": {"name": "x1", "N": 3, "cub_degree": 6,
+           "column": {"n": [3, 3, 60], "lo": [0.0, 0.0, 0.0], "hi": [0.3, 0.3, 6.0], "perturb": 0.2, "seed": 0,
+                      "periodic": [True, True, False]},
+           "pml": {"lo": [-1e9, -1e9, 1.0], "hi": [1e9, 1e9, 5.0], "L": [1.0, 1.0, 1.0],
+                   "sigma_max": [0.0, 0.0, 20.0], "order": 2.0, "kappa_max": 1.0},
+           "alpha": 1.0, "plane_pulse": {"z0": 2.0, "width": 0.2}, "probe": [0.15, 0.15, 3.0],
+           "t_end": 8.0, "t_split": 2.5, "source": None, "probes": None, "cfl": CFL,
+           "scan": {"sigma_max": [1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0, 512.0], "N": [2, 3, 4]}},
     # Differentiation form: the 48,000-tet N=3 mesh and cubic profile of c2, a Gaussian Ez pulse at the
     # origin that reaches the layer within the 500 steps, loss = time-integrated energy in the shell
     # 0.1 inside the PML interface.
@@ -109,6 +125,22 @@ def config(name: str, **overrides) -> dict:
 def mesh_for(cfg: dict):
     m = cfg["mesh"]
     return kuhn_box(m["n"], m["lo"], m["hi"], m.get("perturb", 0.0), m.get("seed", 0))
+
+
+def column_for(cfg: dict):
+    """(vxyz, etov, vertex_id) of a recipe's periodic column."""
+    c = cfg["column"]
+    return kuhn_grid(c["n"], c["lo"], c["hi"], c.get("perturb", 0.0), c.get("seed", 0), tuple(c["periodic"]))
+
+
+def plane_pulse_fields(cfg: dict, xnodes: np.ndarray) -> np.ndarray:
+    """Right-going plane pulse E_x = H_y = exp(-((z - z0)/width)^2), state [K, 12, N_p]."""
+    p = cfg["plane_pulse"]
+    g = np.exp(-(((xnodes[..., 2] - p["z0"]) / p["width"]) ** 2))
+    q = np.zeros((xnodes.shape[0], 12, xnodes.shape[1]))
+    q[:, 0] = g
+    q[:, 4] = g
+    return q
 
 
 def load_rule(degree: int):

@@ -43,7 +43,7 @@ _ip = C.POINTER(C.c_int32)
 
 
 class wdg_mesh(C.Structure):
-    _fields_ = [("nv", C.c_int32), ("vxyz", _dp), ("K", C.c_int32), ("etov", _ip)]
+    _fields_ = [("nv", C.c_int32), ("vxyz", _dp), ("K", C.c_int32), ("etov", _ip), ("vertex_id", _ip)]
 
 
 class wdg_method(C.Structure):
@@ -168,7 +168,7 @@ def make_method(N, rule, pml, alpha=1.0, precision=WDG_FP64, flags=0):
     return m
 
 
-def make_mesh(vxyz, etov):
+def make_mesh(vxyz, etov, vertex_id=None):
     v = _f64(vxyz)
     e = np.ascontiguousarray(etov, dtype=np.int32)
     m = wdg_mesh()
@@ -176,15 +176,20 @@ def make_mesh(vxyz, etov):
     m.vxyz = _ptr(v)
     m.K = e.shape[0]
     m.etov = _ptr(e, _ip)
-    m._keep = (v, e)
+    vid = None
+    if vertex_id is not None:
+        vid = np.ascontiguousarray(vertex_id, dtype=np.int32)
+        assert vid.shape == (v.shape[0],)
+        m.vertex_id = _ptr(vid, _ip)
+    m._keep = (v, e, vid)
     return m
 
 
 class Context:
     """Owns a wdg_ctx; host-only contexts need no GPU."""
 
-    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, host_only=False):
-        mesh = make_mesh(vxyz, etov)
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, host_only=False, vertex_id=None):
+        mesh = make_mesh(vxyz, etov, vertex_id)
         meth = make_method(N, rule, pml, alpha, precision, WDG_HOST_ONLY if host_only else 0)
         h = _ctx()
         _check(wdg_create(C.byref(mesh), C.byref(meth), C.byref(h)))
@@ -260,8 +265,8 @@ class Context:
 class Simulation(Context):
     """A device context whose three state buffers are PyTorch CUDA (HIP) tensors."""
 
-    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, device="cuda"):
-        super().__init__(vxyz, etov, N, rule, pml, alpha, precision, host_only=False)
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, device="cuda", vertex_id=None):
+        super().__init__(vxyz, etov, N, rule, pml, alpha, precision, host_only=False, vertex_id=vertex_id)
         nbytes = self.dims.state_bytes
         self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=device) for _ in range(3)]
         _check(wdg_bind_state(self.h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),

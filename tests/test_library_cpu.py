@@ -195,3 +195,25 @@ def test_pml_scheme_errors_on_host_only_context(rules):
     with pytest.raises(wdg.WdgError) as e:
         wdg._check(wdg.wdg_set_pml_scheme(ctx.h, wdg.WDG_PML_CONSTANT, 0, None, None), ctx.h)
     assert e.value.code == wdg.WDG_ESTATE
+
+
+def test_periodic_connectivity_matches_oracle(rules):
+    from oracle.mesh import Mesh
+    from oracle.refel import RefElement
+    vx, ev, vid = inputs.kuhn_grid((3, 3, 6), [0.0] * 3, [0.3, 0.3, 0.6], 0.15, seed=4, periodic=(True, True, False))
+    pml = {"lo": [-1e9, -1e9, 0.1], "hi": [1e9, 1e9, 0.5], "L": [1.0, 1.0, 0.1], "sigma_max": [0.0, 0.0, 5.0],
+           "order": 2.0, "kappa_max": 1.0}
+    ctx = wdg.Context(vx, ev, 2, rules(4), pml, host_only=True, vertex_id=vid)
+    m = Mesh(vx, ev, RefElement(2, *rules(4)), vertex_id=vid)
+    info = ctx.element_info()
+    assert np.array_equal(info["etoe"], m.EToE) and np.array_equal(info["etof"], m.EToF)
+    assert int((info["etoe"] == np.arange(m.K)[:, None]).sum()) == 36  # walls only at the two z ends
+    # without the identification the side faces are walls
+    plain = wdg.Context(vx, ev, 2, rules(4), pml, host_only=True)
+    assert int((plain.element_info()["etoe"] == np.arange(m.K)[:, None]).sum()) > 36
+    bad = vid.copy()
+    bad[bad == bad[ev[0, 1]]] = bad[ev[0, 0]]
+    with pytest.raises(wdg.WdgError):
+        wdg.Context(vx, ev, 2, rules(4), pml, host_only=True, vertex_id=bad)
+    with pytest.raises(wdg.WdgError):
+        wdg.Context(vx, ev, 2, rules(4), pml, host_only=True, vertex_id=np.full(len(vx), len(vx), np.int32))
