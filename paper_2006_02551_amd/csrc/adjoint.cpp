@@ -216,7 +216,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         stages.alloc(static_cast<size_t>(5 * std::min(C, std::max(nsteps, 1)) + 1) * bytes);
         qh.alloc(2 * bytes);
         y.alloc(bytes);
-        z.alloc(static_cast<size_t>(eh_words(S)) * S.nblk * c->rsize);
+        z.alloc(c->waa_identity ? 0 : static_cast<size_t>(eh_words(S)) * S.nblk * c->rsize);  // z = y otherwise
         rtmp.alloc(bytes);
         const size_t ngrad = static_cast<size_t>(std::max(S.nblk_pml, 1)) * 3 * Nq * B;
         grad.alloc(ngrad * sizeof(double));
@@ -278,11 +278,13 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
                     pp.nblk_pml = S.nblk_pml;
                     pp.nblk = S.nblk;
                     pp.Nq = Nq;
+                    pp.waa_identity = c->waa_identity ? 1 : 0;
                     pp.a_next = i == 4 ? 0.0 : kRkA[i + 1];
                     pp.b = kRkB[i];
                     int e = launch_adjoint_prep(c->precision, S.ref.N, pp, s);
                     if (e == 0)
-                        e = adjoint_stage(c, z.p, y.p, qhb(hc), qhb(1 - hc), st(5 * jstep + i), static_cast<double*>(grad.p), dt, s);
+                        e = adjoint_stage(c, c->waa_identity ? y.p : z.p, y.p, qhb(hc), qhb(1 - hc), st(5 * jstep + i),
+                                          static_cast<double*>(grad.p), dt, s);
                     if (e != 0)
                         return fail(c, WDG_EHIP, std::string("adjoint launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
                     hc = 1 - hc;

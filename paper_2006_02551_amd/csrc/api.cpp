@@ -149,6 +149,16 @@ void upload_setup(wdg_ctx* c) {
     c->off_PqT = push(transpose(R.Pq, Np, Nq));
     c->ops.upload(to_real(ops, c->precision).data(), ops.size() * c->rsize);
 
+    // With kappa = 1 the coefficient a of eq. (9) is one, and P_q a^-1 V_q = P_q V_q = M^-1 V_q^T W V_q
+    // is the identity whenever the rule integrates products of two degree-N polynomials exactly.
+    {
+        const Mat PV = matmul(R.Pq, R.Vq, Np, Nq, Np);
+        double dev = 0.0;
+        for (int i = 0; i < Np; ++i)
+            for (int jj = 0; jj < Np; ++jj) dev = std::max(dev, std::fabs(PV[i * Np + jj] - (i == jj ? 1.0 : 0.0)));
+        c->waa_identity = !S.has_kappa && dev < 1e-12;
+    }
+
     // MFMA A-operand fragments (layout in device.hpp): V_q with full tiles (its
     // row count N_q is a run-time value in the kernel), then P_q, D_r, D_s, D_t
     // and LIFT, whose last tile of N_p rows is stored compact.
@@ -227,6 +237,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.dt_scale = c->has_dt_scale ? static_cast<const double*>(c->dt_scale.p) : nullptr;
     p.pml_mats = c->pml_mats.p;
     p.pml_work = c->pml_work.p;
+    p.waa_identity = c->waa_identity ? 1 : 0;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;

@@ -80,6 +80,7 @@ struct wdg_ctx {
     wdg::DevBuf src_slot, src;
     wdg::DevBuf frags;
     bool mfma_ok = false;
+    bool waa_identity = false;  // kappa = 1 and P_q V_q = I to rounding
     int kernel = WDG_KERNEL_SCALAR;
     int tpw = 2;  // tiles per workgroup of the matrix-core kernel
     // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored

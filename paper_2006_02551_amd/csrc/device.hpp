@@ -78,6 +78,9 @@ struct StageParams {
     const void* pml_mats;    // direct matrices or element-constant coefficients (see the layout above)
     void* pml_work;          // direct scheme: [nblk_pml][6][Np][B] vacuum right-hand side of the PML blocks
     int nblk_pml, nblk, Nq;
+    // 1 when kappa = 1 and P_q V_q = I (a rule exact to degree 2N): a = 1 makes the weight-adjusted
+    // inverse P_q a^-1 V_q the identity, and the kernels skip it
+    int waa_identity;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
 };
@@ -91,6 +94,7 @@ struct PrepParams {
     const void* Vq;       // [Nq][Np]
     const void* PqT;      // [Nq][Np]
     int nblk_pml, nblk, Nq;
+    int waa_identity;     // z = y_f on every block (see StageParams)
     double a_next, b;
 };
 

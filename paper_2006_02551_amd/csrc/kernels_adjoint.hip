@@ -55,6 +55,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_prep_kernel(PrepParams p) {
             y[idx] = keep ? an * y[idx] + v : v;
         }
     }
+    // z = y_f everywhere when the weight-adjusted inverse is the identity: the stage then reads y itself
+    if (p.waa_identity) return;
     real zv[Np];
     if (pml) {
 #pragma unroll
