@@ -162,7 +162,9 @@ void upload_setup(wdg_ctx* c) {
     // MFMA A-operand fragments (layout in device.hpp): V_q with full tiles (its
     // row count N_q is a run-time value in the kernel), then P_q, D_r, D_s, D_t
     // and LIFT, whose last tile of N_p rows is stored compact.
-    c->mfma_ok = mfma_supported(R.N, Nq, c->precision);
+    // (the matrix-core kernel addresses neighbour traces with 32-bit byte offsets into the E,H part)
+    c->mfma_ok = mfma_supported(R.N, Nq, c->precision) &&
+                 static_cast<double>(S.nblk) * eh_words(S) * c->rsize < 4294967296.0;
     if (c->mfma_ok) {
         const int PT = (Np + 15) / 16, SP = (Np + 3) / 4, QT = (Nq + 15) / 16, SQM = 4 * QT, SF = Nfp;
         const bool f64 = c->precision == WDG_FP64;

@@ -93,11 +93,25 @@ __device__ __forceinline__ void stage_rows(const char* __restrict__ base, size_t
         int byte = c * 1024 + lane * 16;
         if (byte >= total) byte = total - 16;  // stays inside the source rows; lands in LDS padding
         const int seg = byte / seg_bytes, off = byte - seg * seg_bytes;
-        __builtin_amdgcn_global_load_lds(base + seg * stride_bytes + off, lds + c * 1024, 16, 0, 0);
+        // uniform base + 32-bit lane offset (the rows of one tile span far less than 4 GiB)
+        const unsigned lofs = static_cast<unsigned>(seg) * static_cast<unsigned>(stride_bytes) + static_cast<unsigned>(off);
+        __builtin_amdgcn_global_load_lds(base + lofs, lds + c * 1024, 16, 0, 0);
     }
 }
 
 constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
+
+// Per-lane global accesses as a wave-uniform base (scalar registers) plus a 32-bit lane
+// offset in elements: the scalar-base addressing form, with constant node offsets folded
+// into the instruction.  The offsets must stay below 4 GiB in bytes (checked on the host).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off * static_cast<unsigned>(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, unsigned off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off * static_cast<unsigned>(sizeof(T))) = v;
+}
 
 // Compile-time shape of the kernel for one precision, order and number of
 // cubature tiles.
@@ -234,16 +248,17 @@ void stage_mfma_kernel(StageParams p) {
                 vw[r][it] = vv;
                 loc[r][it] = in_tile ? (rel >> 6) * T + (rel & (B - 1)) : -1;
                 if (!in_tile) {
-                    const real* __restrict__ qp = qin + off;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) nb[r][it][c] = qp[c * Np * B];
+                    for (int c = 0; c < 6; ++c) nb[r][it][c] = ldg(qin + c * Np * B, static_cast<unsigned>(off));
                 }
             }
     }
 
     // ---- per-wave loads that only this wave needs, issued to overlap the flux phase
-    const size_t pbase = static_cast<size_t>(p.nblk) * EHS + static_cast<size_t>(blk) * EHS + e;
-    const size_t ebase = static_cast<size_t>(blk) * EHS + e;
+    // wave-uniform offsets of this tile's component-u rows (E,H part and auxiliary part); a lane
+    // adds j + node * B
+    const size_t ebase = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + T * sub;
+    const size_t pbase = static_cast<size_t>(p.nblk) * EHS + ebase;
     real* __restrict__ rs = static_cast<real*>(p.res);  // forward: residual; adjoint: stage adjoint y (read only)
     real* __restrict__ qo = static_cast<real*>(p.q_out);
     // base of the update (forward: q_in; adjoint: the running adjoint) and the
@@ -257,7 +272,7 @@ void stage_mfma_kernel(StageParams p) {
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
         const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-        bp[s] = pml ? pin[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+        bp[s] = pml ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
     }
 #pragma unroll
     for (int t = 0; t < PT; ++t)
@@ -265,10 +280,10 @@ void stage_mfma_kernel(StageParams p) {
         for (int v = 0; v < 4; ++v) {
             const int node = 16 * t + 4 * v + g;
             const int nd = node < Np ? node : 0;
-            rP[t][v] = (!ADJ && pml && read_res) ? rs[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-            qP[t][v] = pml ? qb[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-            rE[t][v] = ADJ ? qb[ebase + static_cast<size_t>(u * Np + nd) * B]
-                           : (read_res ? rs[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0));
+            const unsigned lo = static_cast<unsigned>(j + nd * B);
+            rP[t][v] = (!ADJ && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
+            qP[t][v] = pml ? ldg(qb + pbase, lo) : real(0);
+            rE[t][v] = ADJ ? ldg(qb + ebase, lo) : (read_res ? ldg(rs + ebase, lo) : real(0));
         }
     // adjoint: this component's forward fields at the stage input, for the sigma gradient
     constexpr int SPA = ADJ ? SP : 1;
@@ -279,8 +294,8 @@ void stage_mfma_kernel(StageParams p) {
         for (int s = 0; s < SP; ++s) {
             const int node = 4 * s + g;
             const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-            ff[s] = pml ? qf[ebase + static_cast<size_t>(u * Np + nd) * B] : real(0);
-            fp[s] = pml ? qf[pbase + static_cast<size_t>(u * Np + nd) * B] : real(0);
+            ff[s] = pml ? ldg(qf + ebase, static_cast<unsigned>(j + nd * B)) : real(0);
+            fp[s] = pml ? ldg(qf + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
         }
     }
 
@@ -479,13 +494,13 @@ void stage_mfma_kernel(StageParams p) {
             for (int v = 0; v < 4; ++v) {
                 const int node = 16 * t + 4 * v + g;
                 if (node < Np) {
-                    const size_t idx = pbase + static_cast<size_t>(u * Np + node) * B;
+                    const unsigned lo = static_cast<unsigned>(j + node * B);
                     if constexpr (ADJ) {
-                        qo[idx] = qP[t][v] + dt * RP[t][v];
+                        stg(qo + pbase, lo, qP[t][v] + dt * RP[t][v]);
                     } else {
                         const real r = dt * RP[t][v] + rkA * rP[t][v];
-                        rs[idx] = r;
-                        qo[idx] = qP[t][v] + rkB * r;
+                        stg(rs + pbase, lo, r);
+                        stg(qo + pbase, lo, qP[t][v] + rkB * r);
                     }
                 }
             }
@@ -561,14 +576,14 @@ void stage_mfma_kernel(StageParams p) {
         for (int v = 0; v < 4; ++v) {
             const int node = 16 * t + 4 * v + g;
             if (node < Np) {
-                const size_t idx = ebase + static_cast<size_t>(u * Np + node) * B;
+                const unsigned lo = static_cast<unsigned>(j + node * B);
                 if constexpr (ADJ) {
                     // L* y = -L_vac(-alpha) z + P_q(-b VZ + kappa^-1 VY) = -R
-                    qo[idx] = rE[t][v] - dt * R[t][v];
+                    stg(qo + ebase, lo, rE[t][v] - dt * R[t][v]);
                 } else {
                     const real r = dt * R[t][v] + rkA * rE[t][v];
-                    rs[idx] = r;
-                    qo[idx] = ehv(u, node) + rkB * r;
+                    stg(rs + ebase, lo, r);
+                    stg(qo + ebase, lo, ehv(u, node) + rkB * r);
                 }
             }
         }
