@@ -94,8 +94,11 @@ void shell_energy_into(wdg_ctx* c, const ShellDev& sd, const void* q, double sca
     if (e != 0) throw Error(WDG_EHIP, std::string("shell energy launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
 }
 
+// y_next (optional): also write yn_a * (y_scale * y) + yn_b * qhat_out, with y the stage input
+// (weight-adjusted inverse = identity only, where z is y itself up to the factor y_scale)
 int adjoint_stage(wdg_ctx* c, const void* z, const void* y, const void* qhat_in, void* qhat_out, const void* q_fwd,
-                  double* grad, double dt, hipStream_t s) {
+                  double* grad, double dt, hipStream_t s, void* y_next = nullptr, double yn_a = 0.0, double yn_b = 0.0,
+                  double y_scale = 1.0) {
     const Setup& S = c->S;
     StageParams p{};
     p.q_in = z;
@@ -123,6 +126,10 @@ int adjoint_stage(wdg_ctx* c, const void* z, const void* y, const void* qhat_in,
     p.dt = dt;
     p.alpha = -S.flux_alpha;  // the upwind penalty changes sign in the adjoint
     p.src_g = 0.0;
+    p.y_next = y_next;
+    p.yn_a = yn_a;
+    p.yn_b = yn_b;
+    p.y_scale = y_scale;
     return launch_adjoint_mfma(c->precision, S.ref.N, p, s);
 }
 
@@ -199,6 +206,8 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
     if (S.has_kappa) return fail(c, WDG_EINVAL, "the adjoint needs kappa = 1");
     if (c->has_dt_scale) return fail(c, WDG_EINVAL, "the adjoint needs one time step for all elements");
     if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_EINVAL, "the adjoint is built for the weight-adjusted scheme");
+    // kappa = 1 and a rule exact to degree 2N (checked at creation) make P_q a^-1 V_q the identity
+    if (!c->waa_identity) return fail(c, WDG_EINVAL, "the adjoint needs P_q V_q = I");
     if (!adjoint_supported(S.ref.N, S.ref.Nq, c->precision))
         return fail(c, WDG_EINVAL, "no adjoint kernel for this order, rule size and precision");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -210,18 +219,19 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         const int nseg = (nsteps + C - 1) / C;
         ShellDev sd;
         build_shell(c, *shell, sd);
-        DevBuf acc, ckpt, stages, qh, y, z, rtmp, grad;
+        DevBuf acc, ckpt, stages, qh, y, rtmp, grad;
+        int yc = 0;  // current half of y
         acc.alloc(sizeof(double));
         ckpt.alloc(static_cast<size_t>(std::max(nseg, 1)) * bytes);
         stages.alloc(static_cast<size_t>(5 * std::min(C, std::max(nsteps, 1)) + 1) * bytes);
         qh.alloc(2 * bytes);
-        y.alloc(bytes);
-        z.alloc(c->waa_identity ? 0 : static_cast<size_t>(eh_words(S)) * S.nblk * c->rsize);  // z = y otherwise
+        y.alloc(2 * bytes);
         rtmp.alloc(bytes);
         const size_t ngrad = static_cast<size_t>(std::max(S.nblk_pml, 1)) * 3 * Nq * B;
         grad.alloc(ngrad * sizeof(double));
         auto st = [&](int i) { return static_cast<char*>(stages.p) + static_cast<size_t>(i) * bytes; };
         auto qhb = [&](int i) { return static_cast<char*>(qh.p) + static_cast<size_t>(i) * bytes; };
+        auto yb = [&](int i) { return static_cast<char*>(y.p) + static_cast<size_t>(i) * bytes; };
         hip_check(hipMemsetAsync(acc.p, 0, sizeof(double), s), "clear");
 
         // ---- forward sweep: the context's state advances; checkpoints and the loss
@@ -244,7 +254,6 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
 
         // ---- adjoint sweep, segment by segment from the last
         hip_check(hipMemsetAsync(qh.p, 0, bytes, s), "clear");
-        hip_check(hipMemsetAsync(y.p, 0, bytes, s), "clear");
         hip_check(hipMemsetAsync(grad.p, 0, ngrad * sizeof(double), s), "clear");
         int hc = 0;
         for (int seg = nseg - 1; seg >= 0; --seg) {
@@ -268,26 +277,20 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
                     const int e = launch_shell_inject(c->precision, S.ref.N, sp, s);
                     if (e != 0) return fail(c, WDG_EHIP, "shell gradient launch");
                 }
+                // Stages reversed: y_i = A_{i+1} y_{i+1} + B_i q_hat (A_5 = 0), q_hat += dt L* y_i.  With
+                // kappa = 1 the weight-adjusted inverse is the identity, so z = y: every stage takes its y
+                // as input and writes the next stage's y (ping-pong halves); the first stage of the step,
+                // y_4 = B_4 q_hat, reads q_hat with dt scaled by B_4 (L* and the sigma gradient are linear in y).
                 for (int i = 4; i >= 0; --i) {
-                    PrepParams pp{};
-                    pp.y = y.p;
-                    pp.q_hat = qhb(hc);
-                    pp.z = z.p;
-                    pp.Vq = cptr(c->ops, c->off_Vq, c->rsize);
-                    pp.PqT = cptr(c->ops, c->off_PqT, c->rsize);
-                    pp.nblk_pml = S.nblk_pml;
-                    pp.nblk = S.nblk;
-                    pp.Nq = Nq;
-                    pp.waa_identity = c->waa_identity ? 1 : 0;
-                    pp.a_next = i == 4 ? 0.0 : kRkA[i + 1];
-                    pp.b = kRkB[i];
-                    int e = launch_adjoint_prep(c->precision, S.ref.N, pp, s);
-                    if (e == 0)
-                        e = adjoint_stage(c, c->waa_identity ? y.p : z.p, y.p, qhb(hc), qhb(1 - hc), st(5 * jstep + i),
-                                          static_cast<double*>(grad.p), dt, s);
+                    const void* in = i == 4 ? static_cast<const void*>(qhb(hc)) : static_cast<const void*>(yb(yc));
+                    const double scale = i == 4 ? kRkB[4] : 1.0;
+                    void* out = i > 0 ? yb(1 - yc) : nullptr;
+                    const int e = adjoint_stage(c, in, in, qhb(hc), qhb(1 - hc), st(5 * jstep + i), static_cast<double*>(grad.p),
+                                                dt * scale, s, out, i > 0 ? kRkA[i] : 0.0, i > 0 ? kRkB[i - 1] : 0.0, scale);
                     if (e != 0)
                         return fail(c, WDG_EHIP, std::string("adjoint launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
                     hc = 1 - hc;
+                    if (i > 0) yc = 1 - yc;
                 }
             }
         }

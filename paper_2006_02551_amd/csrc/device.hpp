@@ -75,6 +75,11 @@ struct StageParams {
     const double* cub_w;  // [Nq] cubature weights
     const double* Jk;     // [nblk][B] Jacobians
     const double* dt_scale;  // [nblk][B] per-element factor on dt, or null (uniform dt)
+    // adjoint stage, weight-adjusted inverse = identity: also write the next stage's adjoint
+    // y_next = yn_a * (y_scale * y) + yn_b * q_hat_out (null: not written); y is this stage's
+    // input (q_in / res), given as y / y_scale
+    void* y_next;
+    double yn_a, yn_b, y_scale;
     const void* pml_mats;    // direct matrices or element-constant coefficients (see the layout above)
     void* pml_work;          // direct scheme: [nblk_pml][6][Np][B] vacuum right-hand side of the PML blocks
     int nblk_pml, nblk, Nq;
@@ -83,19 +88,6 @@ struct StageParams {
     int waa_identity;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
-};
-
-// Adjoint stage preparation: y <- a_next y + b q_hat (a_next = 0 drops the old
-// y), z = P_q V_q y_f on PML blocks (kappa = 1), z = y_f elsewhere.
-struct PrepParams {
-    void* y;              // stage adjoint, state layout, updated in place
-    const void* q_hat;    // running adjoint, state layout
-    void* z;              // [nblk][6][Np][B]
-    const void* Vq;       // [Nq][Np]
-    const void* PqT;      // [Nq][Np]
-    int nblk_pml, nblk, Nq;
-    int waa_identity;     // z = y_f on every block (see StageParams)
-    double a_next, b;
 };
 
 // Shell-energy loss and its gradient on the blocks holding shell points.
@@ -139,7 +131,6 @@ int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t 
 bool mfma_supported(int N, int Nq, int precision);
 bool adjoint_supported(int N, int Nq, int precision);
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
-int launch_adjoint_prep(int precision, int N, const PrepParams& p, hipStream_t s);
 // partial[sb] = sum over the block's slots of J w_q chi (V_q u)^2 over the six E,H components
 int launch_shell_energy(int precision, int N, const ShellParams& p, hipStream_t s);
 // *acc += scale * sum(partial[0..n)) in a fixed order (one workgroup)

@@ -1,7 +1,5 @@
-// Kernels of the loss-gradient path besides the adjoint stage itself:
-//  - the stage-adjoint update y <- A_{i+1} y + B_i q_hat with the transform
-//    z = P_q a^{-1} V_q y_f of its field part (eq. (21) applied to the
-//    adjoint; a = 1 since kappa = 1), which the adjoint stage then gathers;
+// Kernels of the loss-gradient path besides the adjoint stage itself (which
+// also carries the stage-adjoint update y <- A_{i+1} y + B_i q_hat):
 //  - the shell energy 1/2 sum_k J_k sum_q w_q chi (V_q u)^2 (cubature form,
 //    eqs. (19)-(20)) and its energy-inner-product gradient P_q (chi V_q u).
 // One workgroup per 64-element block, wavefront u = field component u, lane =
@@ -18,64 +16,6 @@ template <int N>
 struct OrdA {
     static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
 };
-
-template <typename real, int N>
-__global__ __launch_bounds__(kThreads) void adjoint_prep_kernel(PrepParams p) {
-    constexpr int Np = OrdA<N>::Np, B = kBlock, EHS = 6 * Np * B;
-    __shared__ real sV[kQmax * Np], sP[kQmax * Np];
-    const int Nq = p.Nq, blk = static_cast<int>(blockIdx.x), tid = static_cast<int>(threadIdx.x);
-    const int u = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < Nq * Np; i += kThreads) {
-        sV[i] = static_cast<const real*>(p.Vq)[i];
-        sP[i] = static_cast<const real*>(p.PqT)[i];
-    }
-    __syncthreads();
-    const bool pml = blk < p.nblk_pml;
-    const real an = static_cast<real>(p.a_next), bi = static_cast<real>(p.b);
-    const bool keep = p.a_next != 0.0;
-    real* y = static_cast<real*>(p.y);
-    const real* qh = static_cast<const real*>(p.q_hat);
-    real yv[Np];
-    {
-        const size_t base = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
-#pragma unroll
-        for (int i = 0; i < Np; ++i) {
-            const size_t idx = base + static_cast<size_t>(i) * B;
-            const real v = bi * qh[idx];
-            yv[i] = keep ? an * y[idx] + v : v;
-            y[idx] = yv[i];
-        }
-    }
-    if (pml) {
-        const size_t base = static_cast<size_t>(p.nblk + blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
-#pragma unroll
-        for (int i = 0; i < Np; ++i) {
-            const size_t idx = base + static_cast<size_t>(i) * B;
-            const real v = bi * qh[idx];
-            y[idx] = keep ? an * y[idx] + v : v;
-        }
-    }
-    // z = y_f everywhere when the weight-adjusted inverse is the identity: the stage then reads y itself
-    if (p.waa_identity) return;
-    real zv[Np];
-    if (pml) {
-#pragma unroll
-        for (int i = 0; i < Np; ++i) zv[i] = real(0);
-        for (int q = 0; q < Nq; ++q) {
-            real v = real(0);
-#pragma unroll
-            for (int jj = 0; jj < Np; ++jj) v += sV[q * Np + jj] * yv[jj];
-#pragma unroll
-            for (int i = 0; i < Np; ++i) zv[i] += sP[q * Np + i] * v;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < Np; ++i) zv[i] = yv[i];
-    }
-    real* z = static_cast<real*>(p.z) + static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
-#pragma unroll
-    for (int i = 0; i < Np; ++i) z[static_cast<size_t>(i) * B] = zv[i];
-}
 
 template <typename real, int N>
 __global__ __launch_bounds__(kThreads) void shell_energy_kernel(ShellParams p) {
@@ -162,19 +102,6 @@ __global__ __launch_bounds__(kThreads) void shell_inject_kernel(ShellParams p) {
 }
 
 template <typename real>
-int prep_n(int N, const PrepParams& p, hipStream_t s) {
-    const dim3 g(p.nblk), b(kThreads);
-    switch (N) {
-        case 1: hipLaunchKernelGGL((adjoint_prep_kernel<real, 1>), g, b, 0, s, p); break;
-        case 2: hipLaunchKernelGGL((adjoint_prep_kernel<real, 2>), g, b, 0, s, p); break;
-        case 3: hipLaunchKernelGGL((adjoint_prep_kernel<real, 3>), g, b, 0, s, p); break;
-        case 4: hipLaunchKernelGGL((adjoint_prep_kernel<real, 4>), g, b, 0, s, p); break;
-        default: return static_cast<int>(hipErrorInvalidValue);
-    }
-    return static_cast<int>(hipGetLastError());
-}
-
-template <typename real>
 int energy_n(int N, const ShellParams& p, hipStream_t s) {
     const dim3 g(p.nsb), b(kThreads);
     switch (N) {
@@ -201,11 +128,6 @@ int inject_n(int N, const ShellParams& p, hipStream_t s) {
 }
 
 }  // namespace
-
-int launch_adjoint_prep(int precision, int N, const PrepParams& p, hipStream_t s) {
-    if (p.Nq > kQmax) return static_cast<int>(hipErrorInvalidValue);
-    return precision == 0 ? prep_n<double>(N, p, s) : prep_n<float>(N, p, s);
-}
 
 int launch_shell_energy(int precision, int N, const ShellParams& p, hipStream_t s) {
     if (p.Nq > kQmax) return static_cast<int>(hipErrorInvalidValue);

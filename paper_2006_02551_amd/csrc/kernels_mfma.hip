@@ -366,6 +366,9 @@ void stage_mfma_kernel(StageParams p) {
     const int bb = (ax == 2) ? 0 : ax + 1;
     const int cc = (ax == 0) ? 2 : ax - 1;
     const real rkA = static_cast<real>(p.rk_a), rkB = static_cast<real>(p.rk_b);
+    // adjoint: y_next = yn_a (y_scale y) + yn_b q_hat_out, y being this stage's input
+    real* __restrict__ yn = ADJ ? static_cast<real*>(p.y_next) : nullptr;
+    const real yna = static_cast<real>(p.yn_a * p.y_scale), ynb = static_cast<real>(p.yn_b);
     // time step of this lane's element (a per-element scale lets independent simulations share a launch)
     const real dt = static_cast<real>(p.dt_scale ? p.dt * p.dt_scale[static_cast<size_t>(blk) * B + e] : p.dt);
 
@@ -496,7 +499,9 @@ void stage_mfma_kernel(StageParams p) {
                 if (node < Np) {
                     const unsigned lo = static_cast<unsigned>(j + node * B);
                     if constexpr (ADJ) {
-                        stg(qo + pbase, lo, qP[t][v] + dt * RP[t][v]);
+                        const real qn = qP[t][v] + dt * RP[t][v];
+                        stg(qo + pbase, lo, qn);
+                        if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
                     } else {
                         const real r = dt * RP[t][v] + rkA * rP[t][v];
                         stg(rs + pbase, lo, r);
@@ -579,7 +584,9 @@ void stage_mfma_kernel(StageParams p) {
                 const unsigned lo = static_cast<unsigned>(j + node * B);
                 if constexpr (ADJ) {
                     // L* y = -L_vac(-alpha) z + P_q(-b VZ + kappa^-1 VY) = -R
-                    stg(qo + ebase, lo, rE[t][v] - dt * R[t][v]);
+                    const real qn = rE[t][v] - dt * R[t][v];
+                    stg(qo + ebase, lo, qn);
+                    if (yn) stg(yn + ebase, lo, yna * ehv(u, node) + ynb * qn);
                 } else {
                     const real r = dt * R[t][v] + rkA * rE[t][v];
                     stg(rs + ebase, lo, r);
