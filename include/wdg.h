@@ -196,8 +196,7 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
 #define WDG_KERNEL_MFMA 2
 
 /* Selects the stage-kernel variant; WDG_EINVAL if MFMA is not available for
- * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64,
- * FP32 only). */
+ * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64). */
 int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
 
 /* ---- PML schemes compared with the weight-adjusted one ------------------- */
@@ -238,7 +237,8 @@ int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
 int32_t wdg_set_pml_scheme(wdg_ctx* ctx, int32_t scheme, int32_t nr, const double* rst, const double* w);
 
 /* Tiles of 16 elements per workgroup of the matrix-core kernel: 1 or 2 (the
- * default).  Results do not depend on it. */
+ * default where two fit in a compute unit's LDS; FP64 at N = 4 takes one,
+ * WDG_EINVAL for two).  Results do not depend on it. */
 int32_t wdg_set_tiles(wdg_ctx* ctx, int32_t tiles);
 
 /* Times the available stage kernels (scalar-operand; matrix-core with 1 and 2

@@ -165,6 +165,8 @@ void upload_setup(wdg_ctx* c) {
     // (the matrix-core kernel addresses neighbour traces with 32-bit byte offsets into the E,H part)
     c->mfma_ok = mfma_supported(R.N, Nq, c->precision) &&
                  static_cast<double>(S.nblk) * eh_words(S) * c->rsize < 4294967296.0;
+    // two tiles per workgroup where they fit in LDS (FP64 at N = 4 takes one)
+    if (c->mfma_ok && !mfma_tiles_fit(R.N, Nq, c->precision, c->tpw)) c->tpw = 1;
     if (c->mfma_ok) {
         const int PT = (Np + 15) / 16, SP = (Np + 3) / 4, QT = (Nq + 15) / 16, SQM = 4 * QT, SF = Nfp;
         const bool f64 = c->precision == WDG_FP64;

@@ -41,6 +41,8 @@ extern "C" {
 int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
     if (!c) return WDG_EINVAL;
     if (tiles != 1 && tiles != 2) return fail(c, WDG_EINVAL, "tiles per workgroup must be 1 or 2");
+    if (c->mfma_ok && !mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, tiles))
+        return fail(c, WDG_EINVAL, "this many tiles per workgroup need more LDS than a compute unit has");
     c->tpw = tiles;
     return WDG_OK;
 }
@@ -173,7 +175,9 @@ int32_t wdg_autotune(wdg_ctx* c, int32_t reps, double* times_us, void* hip_strea
         for (int i = 0; i < 3 && rc == WDG_OK; ++i) {
             double t_us = -1.0;
             // the matrix-core kernel runs the weight-adjusted scheme only
-            if (cands[i].kernel != WDG_KERNEL_MFMA || (c->mfma_ok && c->pml_scheme == WDG_PML_WAA)) {
+            if (cands[i].kernel != WDG_KERNEL_MFMA ||
+                (c->mfma_ok && c->pml_scheme == WDG_PML_WAA &&
+                 mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, cands[i].tpw))) {
                 c->kernel = cands[i].kernel;
                 c->tpw = cands[i].tpw;
                 // a stage as in the middle of a step: reads and writes the residual,

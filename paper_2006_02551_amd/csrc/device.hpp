@@ -129,6 +129,8 @@ int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const Stage
 // Adjoint stage on the matrix cores (kappa = 1; same (N, N_q) support as the forward).
 int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s);
 bool mfma_supported(int N, int Nq, int precision);
+// whether the matrix-core kernel with tpw tiles per workgroup fits in a compute unit's LDS
+bool mfma_tiles_fit(int N, int Nq, int precision, int tpw);
 bool adjoint_supported(int N, int Nq, int precision);
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s);
 // partial[sb] = sum over the block's slots of J w_q chi (V_q u)^2 over the six E,H components

@@ -140,12 +140,17 @@ struct Shape {
     // KiB for the staging copies), and per tile the flux of one round
     static constexpr int L_FR = pad1k(NW * RB);
     static constexpr int L_EH = pad1k(6 * Np * T * RB);
-    static constexpr int L_SG = pad1k(3 * QMAX * T * RB);
+    static constexpr int L_SG0 = pad1k(3 * QMAX * T * RB);
     static constexpr int L_GE = pad1k(kGeo * T * RB);
     static constexpr int L_NB = pad1k(NF * T * 4);
-    static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
     static constexpr int L_FL = 6 * NFH * T * RB;
     static constexpr int L_GL = ADJ ? 3 * QMAX * T * RB : 0;  // adjoint: sigma-gradient accumulator
+    // Where the workgroup would not fit in the 160 KiB of LDS otherwise, sigma (needed only in the
+    // PML phase) is staged into the flux buffer after the flux rounds instead of with the tile.
+    static constexpr bool SGFL =
+        L_FR + TPW * (L_EH + L_SG0 + L_GE + L_NB + L_FL + L_GL) > 160 * 1024 && L_FL >= L_SG0;
+    static constexpr int L_SG = SGFL ? 0 : L_SG0;
+    static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
     static constexpr int LDS = L_FR + TPW * (L_TL + L_FL + L_GL);
     // Register budget: as many wavefronts per SIMD as the workgroups that fit
     // in the 160 KiB of LDS of a compute unit bring (at most 6, 80 VGPRs).
@@ -178,7 +183,8 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int RB = S::RB;
     constexpr int L_FR = S::L_FR, L_EH = S::L_EH, L_SG = S::L_SG, L_GE = S::L_GE, L_TL = S::L_TL;
     __shared__ __attribute__((aligned(16))) char smem[L_FR + TPW * L_TL];
-    __shared__ real fls[TPW][6 * NFH * T];  // flux [component][face node of the round][element of the tile]
+    // flux [component][face node of the round][element of the tile]; sigma rows after the flux when S::SGFL
+    __shared__ __attribute__((aligned(16))) real fls[TPW][6 * NFH * T];
     __shared__ real gls[ADJ ? TPW * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
 
     // Workgroup: TPW adjacent tiles of one element block, six
@@ -189,7 +195,7 @@ void stage_mfma_kernel(StageParams p) {
     real* fr = reinterpret_cast<real*>(smem);
     char* tl = smem + L_FR + h * L_TL;
     real* eh = reinterpret_cast<real*>(tl);
-    real* sgs = reinterpret_cast<real*>(tl + L_EH);
+    real* sgs = S::SGFL ? fls[h] : reinterpret_cast<real*>(tl + L_EH);
     real* ges = reinterpret_cast<real*>(tl + L_EH + L_SG);
     int* nbs = reinterpret_cast<int*>(tl + L_EH + L_SG + L_GE);
     real* fl = fls[h];
@@ -220,7 +226,7 @@ void stage_mfma_kernel(StageParams p) {
                    row, T * RB, kGeo, tl + L_EH + L_SG, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(p.nbr + static_cast<size_t>(blk) * NF * B + T * sub), static_cast<size_t>(B) * 4,
                    T * 4, NF, tl + L_EH + L_SG + L_GE, u, 6, lane);
-        if (pml)
+        if (pml && !S::SGFL)
             stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
                        row, T * RB, 3 * Nq, tl + L_EH, u, 6, lane);
     }
@@ -267,7 +273,7 @@ void stage_mfma_kernel(StageParams p) {
     const real* __restrict__ pin = ADJ ? static_cast<const real*>(p.res) : qin;
     const bool read_res = p.read_res != 0;
     real bp[SP];
-    real rP[PT][4], qP[PT][4], rE[PT][4];  // adjoint: rE holds the E,H base, rP is unused
+    real rP[PT][4], qP[PT][4], rE[PT][4];  // adjoint: qP, rE hold the update base (FP64)
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
@@ -282,8 +288,10 @@ void stage_mfma_kernel(StageParams p) {
             const int nd = node < Np ? node : 0;
             const unsigned lo = static_cast<unsigned>(j + nd * B);
             rP[t][v] = (!ADJ && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
-            qP[t][v] = pml ? ldg(qb + pbase, lo) : real(0);
-            rE[t][v] = ADJ ? ldg(qb + ebase, lo) : (read_res ? ldg(rs + ebase, lo) : real(0));
+            // (the FP32 adjoint reads its update base where it is used: fewer registers live at
+            // its two-workgroup occupancy)
+            qP[t][v] = ((!ADJ || F64) && pml) ? ldg(qb + pbase, lo) : real(0);
+            rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0)) : (read_res ? ldg(rs + ebase, lo) : real(0));
         }
     // adjoint: this component's forward fields at the stage input, for the sigma gradient
     constexpr int SPA = ADJ ? SP : 1;
@@ -361,6 +369,14 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
+    if constexpr (S::SGFL) {
+        // every wave has finished reading the flux buffer: stage sigma into it (waited for before A)
+        __syncthreads();
+        if (pml)
+            stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
+                       static_cast<size_t>(B) * RB, T * RB, 3 * Nq, reinterpret_cast<char*>(fl), u, 6, lane);
+    }
+
     const int SQ = (Nq + 3) / 4;
     const int ax = (u < 3) ? u : u - 3;
     const int bb = (ax == 2) ? 0 : ax + 1;
@@ -395,46 +411,45 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
+    if constexpr (S::SGFL) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+
     // ---- A. PML terms at the cubature points (eqs. (26)-(29))
     if (pml) {
         const real* __restrict__ kp =
             KAPPA ? static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + e : nullptr;
-        // forward: VF = V_q f_u, VP = V_q P_u; adjoint: VF = V_q z_u, VP = V_q y_{P,u}
-        // and, for the gradient, VFf = V_q f_u, VPf = V_q P_u of the forward stage input
-        constexpr int QTA = ADJ ? QT : 1;
-        v4 VF[QT], VP[QT], VFf[QTA], VPf[QTA];
+        // One cubature tile (16 points) at a time, so that only its products are live:
+        // forward: VF = V_q f_u, VP = V_q P_u; adjoint: VF = V_q z_u, VP = V_q y_{P,u} and, for
+        // the gradient, VFf = V_q f_u, VPf = V_q P_u of the forward stage input.  Then eq. (9) at
+        // cubature point q = 16 tq + 4 v + g.  Forward: VF <- -t1, VP <- t2.  Adjoint: VF <- b VZ -
+        // kappa^-1 VY, VP <- -c VZ - d VY, and the node's sigma gradient (kappa = 1: db/dsigma_(u,v,w)
+        // = (-1, 1, 1), dc/dsigma_(u,v,w) = (sigma_u - b, sigma_w - sigma_u, sigma_v - sigma_u),
+        // dd/dsigma_u = 1) goes to the LDS accumulator, weighted by dt J w_q.  Last rhs_P += P_q t2 and
+        // R -= P_q t1 over the tile's k-steps.
+        const double wJ = ADJ ? p.dt * p.Jk[static_cast<size_t>(blk) * B + e] : 0.0;
+        v4 RP[PT];
 #pragma unroll
-        for (int t = 0; t < QT; ++t) VF[t] = VP[t] = v4{0, 0, 0, 0};
+        for (int t = 0; t < PT; ++t) RP[t] = v4{0, 0, 0, 0};
 #pragma unroll
-        for (int t = 0; t < QTA; ++t) VFf[t] = VPf[t] = v4{0, 0, 0, 0};
+        for (int tq = 0; tq < QT; ++tq) {
+            v4 VF = v4{0, 0, 0, 0}, VP = v4{0, 0, 0, 0}, VFf = v4{0, 0, 0, 0}, VPf = v4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < SP; ++s) {
-            const int node = 4 * s + g;
-            const bool ok = (SP * 4 == Np) || node < Np;
-            const real bf = ok ? ehv(u, node) : real(0);
-            const real bpv = ok ? bp[s] : real(0);
-#pragma unroll
-            for (int t = 0; t < QT; ++t) {
-                const real a = fragq(t, s);
-                VF[t] = M::run(a, bf, VF[t]);
-                VP[t] = M::run(a, bpv, VP[t]);
+            for (int s = 0; s < SP; ++s) {
+                const int node = 4 * s + g;
+                const bool ok = (SP * 4 == Np) || node < Np;
+                const real a = fragq(tq, s);
+                VF = M::run(a, ok ? ehv(u, node) : real(0), VF);
+                VP = M::run(a, ok ? bp[s] : real(0), VP);
                 if constexpr (ADJ) {
-                    VFf[t] = M::run(a, ok ? ff[s] : real(0), VFf[t]);
-                    VPf[t] = M::run(a, ok ? fp[s] : real(0), VPf[t]);
+                    VFf = M::run(a, ok ? ff[s] : real(0), VFf);
+                    VPf = M::run(a, ok ? fp[s] : real(0), VPf);
                 }
             }
-        }
-        // eq. (9) at cubature point q = 16 t + 4 v + g.  Forward: VF <- -t1,
-        // VP <- t2.  Adjoint: VF <- b VZ - kappa^-1 VY, VP <- -c VZ - d VY, and
-        // the node's sigma gradient (kappa = 1: db/dsigma_(u,v,w) = (-1, 1, 1),
-        // dc/dsigma_(u,v,w) = (sigma_u - b, sigma_w - sigma_u, sigma_v - sigma_u),
-        // dd/dsigma_u = 1) goes to the LDS accumulator, weighted by dt J w_q.
-        const double wJ = ADJ ? p.dt * p.Jk[static_cast<size_t>(blk) * B + e] : 0.0;
-#pragma unroll
-        for (int t = 0; t < QT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int q = 16 * t + 4 * v + g;
+                const int q = 16 * tq + 4 * v + g;
                 real t1 = real(0), t2 = real(0);
                 if (q < Nq) {
                     const real sa = sgs[(ax * Nq + q) * T + j], sbq = sgs[(bb * Nq + q) * T + j], scq = sgs[(cc * Nq + q) * T + j];
@@ -452,9 +467,9 @@ void stage_mfma_kernel(StageParams p) {
                         cq = sbq * scq - bq * sa;
                         dq = sa;
                     }
-                    const real vf = VF[t][v], vp = VP[t][v];
+                    const real vf = VF[v], vp = VP[v];
                     if constexpr (ADJ) {
-                        const real vff = VFf[t][v], vpf = VPf[t][v];
+                        const real vff = VFf[v], vpf = VPf[v];
                         const real w = static_cast<real>(wJ * p.cub_w[q]);
                         const real gu = -vf * (-vff + (sa - bq) * vpf) - vp * vpf;
                         const real gv = -vf * (vff + (scq - sa) * vpf);
@@ -469,15 +484,9 @@ void stage_mfma_kernel(StageParams p) {
                         t2 = kinv * vf - dq * vp;
                     }
                 }
-                VF[t][v] = -t1;
-                VP[t][v] = t2;
+                VF[v] = -t1;
+                VP[v] = t2;
             }
-        // rhs_P = P_q t2 and R -= P_q t1
-        v4 RP[PT];
-#pragma unroll
-        for (int t = 0; t < PT; ++t) RP[t] = v4{0, 0, 0, 0};
-#pragma unroll
-        for (int tq = 0; tq < QT; ++tq)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int sq = 4 * tq + v;
@@ -485,11 +494,12 @@ void stage_mfma_kernel(StageParams p) {
 #pragma unroll
                     for (int t = 0; t < PT; ++t) {
                         const real a = frag(OFF_PQ, t, sq, SQM);
-                        RP[t] = M::run(a, VP[tq][v], RP[t]);
-                        R[t] = M::run(a, VF[tq][v], R[t]);
+                        RP[t] = M::run(a, VP[v], RP[t]);
+                        R[t] = M::run(a, VF[v], R[t]);
                     }
                 }
             }
+        }
         // LSERK update of the auxiliary component
 #pragma unroll
         for (int t = 0; t < PT; ++t)
@@ -499,7 +509,7 @@ void stage_mfma_kernel(StageParams p) {
                 if (node < Np) {
                     const unsigned lo = static_cast<unsigned>(j + node * B);
                     if constexpr (ADJ) {
-                        const real qn = qP[t][v] + dt * RP[t][v];
+                        const real qn = (F64 ? qP[t][v] : ldg(qb + pbase, lo)) + dt * RP[t][v];
                         stg(qo + pbase, lo, qn);
                         if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
                     } else {
@@ -584,7 +594,7 @@ void stage_mfma_kernel(StageParams p) {
                 const unsigned lo = static_cast<unsigned>(j + node * B);
                 if constexpr (ADJ) {
                     // L* y = -L_vac(-alpha) z + P_q(-b VZ + kappa^-1 VY) = -R
-                    const real qn = rE[t][v] - dt * R[t][v];
+                    const real qn = (F64 ? rE[t][v] : ldg(qb + ebase, lo)) - dt * R[t][v];
                     stg(qo + ebase, lo, qn);
                     if (yn) stg(yn + ebase, lo, yna * ehv(u, node) + ynb * qn);
                 } else {
@@ -657,12 +667,18 @@ int launch_r(int N, int QT, bool k, int tpw, const StageParams& p, hipStream_t s
     }
 }
 
+template <typename real>
 int launch_r4(int QT, bool k, int tpw, const StageParams& p, hipStream_t s) {
     switch (QT) {
-        case 3: return launch_k<float, 4, 3>(k, tpw, p, s);
-        case 4: return launch_k<float, 4, 4>(k, tpw, p, s);
+        case 3: return launch_k<real, 4, 3>(k, tpw, p, s);
+        case 4: return launch_k<real, 4, 4>(k, tpw, p, s);
         default: return -1;
     }
+}
+
+template <typename real, int N, int QT>
+constexpr bool fits(int tpw) {
+    return tpw == 1 ? Shape<real, N, QT, false, 1>::LDS <= 160 * 1024 : Shape<real, N, QT, false, 2>::LDS <= 160 * 1024;
 }
 
 }  // namespace
@@ -687,8 +703,24 @@ bool adjoint_supported(int N, int Nq, int precision) {
 bool mfma_supported(int N, int Nq, int precision) {
     const int QT = (Nq + 15) / 16;
     switch (N * 10 + QT) {
-        case 11: case 12: case 21: case 22: case 32: case 33: return true;
-        case 43: case 44: return precision != 0;
+        case 11: case 12: case 21: case 22: case 32: case 33: case 43: case 44: return true;
+        default: return false;
+    }
+}
+
+bool mfma_tiles_fit(int N, int Nq, int precision, int tpw) {
+    if (!mfma_supported(N, Nq, precision)) return false;
+    const int QT = (Nq + 15) / 16;
+    const bool d = precision == 0;
+    switch (N * 10 + QT) {
+        case 11: return d ? fits<double, 1, 1>(tpw) : fits<float, 1, 1>(tpw);
+        case 12: return d ? fits<double, 1, 2>(tpw) : fits<float, 1, 2>(tpw);
+        case 21: return d ? fits<double, 2, 1>(tpw) : fits<float, 2, 1>(tpw);
+        case 22: return d ? fits<double, 2, 2>(tpw) : fits<float, 2, 2>(tpw);
+        case 32: return d ? fits<double, 3, 2>(tpw) : fits<float, 3, 2>(tpw);
+        case 33: return d ? fits<double, 3, 3>(tpw) : fits<float, 3, 3>(tpw);
+        case 43: return d ? fits<double, 4, 3>(tpw) : fits<float, 4, 3>(tpw);
+        case 44: return d ? fits<double, 4, 4>(tpw) : fits<float, 4, 4>(tpw);
         default: return false;
     }
 }
@@ -702,8 +734,8 @@ int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t 
 
 int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s) {
     const int QT = (p.Nq + 15) / 16;
+    if (N == 4) return precision == 0 ? launch_r4<double>(QT, has_kappa, tpw, p, s) : launch_r4<float>(QT, has_kappa, tpw, p, s);
     if (precision == 0) return launch_r<double>(N, QT, has_kappa, tpw, p, s);
-    if (N == 4) return launch_r4(QT, has_kappa, tpw, p, s);
     return launch_r<float>(N, QT, has_kappa, tpw, p, s);
 }
 

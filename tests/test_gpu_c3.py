@@ -1,9 +1,8 @@
 """The precision form at full size: 40^3 x 6 = 384,000 perturbed tetrahedra,
 N = 4, degree-8 cubature (51 points), quadratic profile sigma_max = 40, dipole.
 
-* the right-hand side of sampled elements against the FP64 oracle (FP64: the
-  scalar-operand kernel, since the FP64 matrix-core kernel at N = 4 needs more
-  LDS than a compute unit has; FP32: the matrix-core kernel);
+* the right-hand side of sampled elements against the FP64 oracle (both
+  precisions on the matrix-core kernel, FP64 with one tile per workgroup);
 * FP32 stepping against FP64 stepping on the GPU over the recipe's 2,000
   steps, relative L2 error of E, H reported at steps 100, 1,000 and 2,000
   (the oracle itself would need hours per hundred steps at this size; the FP64
