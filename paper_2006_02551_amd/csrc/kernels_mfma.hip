@@ -100,6 +100,8 @@ __device__ __forceinline__ void stage_rows(const char* __restrict__ base, size_t
 }
 
 constexpr int pad1k(int bytes) { return (bytes + 1023) / 1024 * 1024; }
+constexpr int kLdsCU = 160 * 1024;  // LDS of a compute unit
+constexpr int wg_per_cu(int lds) { return lds <= kLdsCU ? (kLdsCU / lds < 1 ? 1 : kLdsCU / lds) : 1; }
 
 // Per-lane global accesses as a wave-uniform base (scalar registers) plus a 32-bit lane
 // offset in elements: the scalar-base addressing form, with constant node offsets folded
@@ -124,7 +126,6 @@ struct Shape {
     static constexpr int SP = (Np + 3) / 4;        // k-steps over nodes
     static constexpr int SQM = 4 * QT;             // k-steps reserved over cubature points
     static constexpr int SF = Nfp;                 // k-steps over the face nodes
-    static constexpr int S0 = (SF + 1) / 2;        // k-steps (4 face nodes each) of the first flux round
     static constexpr int QMAX = 16 * QT;           // cubature points the sigma staging can hold
     static constexpr int RB = static_cast<int>(sizeof(real));
     // fragment words of each operator (V_q full tiles; P_q, D_r,s,t, LIFT compact last tile)
@@ -134,7 +135,6 @@ struct Shape {
     static constexpr int W_L = frag_words(Np, PT, SF, true);
     static constexpr int OFF_VQ = 0, OFF_PQ = W_VQ, OFF_D = OFF_PQ + W_PQ, OFF_L = OFF_D + 3 * W_D;
     static constexpr int NW = OFF_L + W_L;
-    static constexpr int NFH = 4 * S0;  // face nodes per flux round (the second round has NF - NFH)
     // LDS: operator fragments (shared by the workgroup), then per tile its E,H
     // rows, sigma rows, geometry rows and neighbour offsets (all padded to whole
     // KiB for the staging copies), and per tile the flux of one round
@@ -143,18 +143,29 @@ struct Shape {
     static constexpr int L_SG0 = pad1k(3 * QMAX * T * RB);
     static constexpr int L_GE = pad1k(kGeo * T * RB);
     static constexpr int L_NB = pad1k(NF * T * 4);
-    static constexpr int L_FL = 6 * NFH * T * RB;
     static constexpr int L_GL = ADJ ? 3 * QMAX * T * RB : 0;  // adjoint: sigma-gradient accumulator
-    // Where the workgroup would not fit in the 160 KiB of LDS otherwise, sigma (needed only in the
-    // PML phase) is staged into the flux buffer after the flux rounds instead of with the tile.
-    static constexpr bool SGFL =
-        L_FR + TPW * (L_EH + L_SG0 + L_GE + L_NB + L_FL + L_GL) > 160 * 1024 && L_FL >= L_SG0;
+    // The flux buffer holds the face nodes of one round: all of them (one round, two barriers
+    // fewer) where that costs no workgroups per compute unit, else the first half.  Where the
+    // workgroup would not fit in LDS otherwise, sigma (needed only in the PML phase) is staged into
+    // the flux buffer after the flux rounds instead of with the tile.
+    static constexpr int L_FL1 = 6 * NF * T * RB, L_FL2 = 6 * 4 * ((SF + 1) / 2) * T * RB;
+    static constexpr int L_NOSG = L_EH + L_GE + L_NB + L_GL;
+    static constexpr bool SG1 = L_FR + TPW * (L_NOSG + L_SG0 + L_FL1) > kLdsCU && L_FL1 >= L_SG0;
+    static constexpr bool SG2 = L_FR + TPW * (L_NOSG + L_SG0 + L_FL2) > kLdsCU && L_FL2 >= L_SG0;
+    static constexpr int LDS1 = L_FR + TPW * (L_NOSG + (SG1 ? 0 : L_SG0) + L_FL1);
+    static constexpr int LDS2 = L_FR + TPW * (L_NOSG + (SG2 ? 0 : L_SG0) + L_FL2);
+    static constexpr bool ONE = LDS1 <= kLdsCU && wg_per_cu(LDS1) == wg_per_cu(LDS2);
+    static constexpr int ROUNDS = ONE ? 1 : 2;
+    static constexpr int S0 = ONE ? SF : (SF + 1) / 2;  // k-steps (4 face nodes each) of the first round
+    static constexpr int NFH = 4 * S0;  // face nodes per flux round (the second round has NF - NFH)
+    static constexpr int L_FL = ONE ? L_FL1 : L_FL2;
+    static constexpr bool SGFL = ONE ? SG1 : SG2;
     static constexpr int L_SG = SGFL ? 0 : L_SG0;
     static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
-    static constexpr int LDS = L_FR + TPW * (L_TL + L_FL + L_GL);
+    static constexpr int LDS = ONE ? LDS1 : LDS2;
     // Register budget: as many wavefronts per SIMD as the workgroups that fit
     // in the 160 KiB of LDS of a compute unit bring (at most 6, 80 VGPRs).
-    static constexpr int WG_PER_CU = LDS <= 160 * 1024 ? (160 * 1024 / LDS < 1 ? 1 : 160 * 1024 / LDS) : 1;
+    static constexpr int WG_PER_CU = wg_per_cu(LDS);
     static constexpr int WAVES_PER_SIMD_RAW = (WG_PER_CU * 6 * TPW + 3) / 4;
     static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_RAW < 6 ? WAVES_PER_SIMD_RAW : 6;
 };
@@ -233,15 +244,15 @@ void stage_mfma_kernel(StageParams p) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- neighbour traces for both flux rounds.  A neighbour inside this tile
+    // ---- neighbour traces for all flux rounds.  A neighbour inside this tile
     // (and the own trace at a PEC wall) is read from the staged E,H rows at
     // flux time (loc >= 0); the others are fetched from global memory now.
-    real nb[2][FIT][6];
-    int loc[2][FIT], vw[2][FIT];
+    real nb[S::ROUNDS][FIT][6];
+    int loc[S::ROUNDS][FIT], vw[S::ROUNDS][FIT];
     {
         const int base = blk * EHS + T * sub;
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < S::ROUNDS; ++r)
 #pragma unroll
             for (int it = 0; it < FIT; ++it) {
                 const int nitem = (r == 0 ? NFH : NF - NFH) * T;
@@ -326,7 +337,7 @@ void stage_mfma_kernel(StageParams p) {
     {
         const real alpha = static_cast<real>(p.alpha);
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < S::ROUNDS; ++r) {
             const int nitem = (r == 0 ? NFH : NF - NFH) * T;
             if (r == 1) __syncthreads();  // the first round's lift has read fl
 #pragma unroll
