@@ -176,7 +176,10 @@ struct Shape {
 // writes q_base + dt L* y to q_out and adds the stage's sigma gradient to
 // p.grad.  Same staging, flux, lift and curl as the forward stage, with the
 // flux parameter negated by the caller.
-template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW>
+//
+// NQ > 0 fixes the number of cubature points at compile time (the stored rules of degree 2N), so that
+// the guards on padded cubature slots resolve at compile time; NQ = 0 reads it from p.Nq.
+template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW, int NQ>
 __global__ __launch_bounds__(TPW * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ, TPW>::WAVES_PER_SIMD)))
 void stage_mfma_kernel(StageParams p) {
     static_assert(!(ADJ && KAPPA), "the adjoint stage is written for kappa = 1");
@@ -215,7 +218,7 @@ void stage_mfma_kernel(StageParams p) {
         TPW * remap_tile(blockIdx.x, 4 / TPW * p.nblk_pml, 4 / TPW * p.nblk) + h);
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
-    const int Nq = p.Nq;
+    const int Nq = NQ > 0 ? NQ : p.Nq;
     const int u = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int g = lane >> 4, j = lane & 15;
@@ -630,13 +633,24 @@ void stage_mfma_kernel(StageParams p) {
     }
 }
 
+// Points of the stored cubature rules of degree 2N.
+template <int N>
+constexpr int rule_nq() { return N == 1 ? 4 : N == 2 ? 14 : N == 3 ? 24 : 51; }
+
 template <typename real, int N, int QT, bool K, bool ADJ, int TPW>
 int launch_t(const StageParams& p, hipStream_t s) {
     if constexpr (Shape<real, N, QT, ADJ, TPW>::LDS > 160 * 1024) {
         return static_cast<int>(hipErrorInvalidConfiguration);  // more LDS than a compute unit has
     } else {
-        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW>), dim3(4 / TPW * p.nblk), dim3(TPW * kMfmaThreads), 0,
-                           s, p);
+        const dim3 grid(4 / TPW * p.nblk), block(TPW * kMfmaThreads);
+        constexpr int RQ = rule_nq<N>();
+        if constexpr (!K && (RQ + 15) / 16 == QT) {
+            if (p.Nq == RQ) {
+                hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
+                return static_cast<int>(hipGetLastError());
+            }
+        }
+        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, 0>), grid, block, 0, s, p);
         return static_cast<int>(hipGetLastError());
     }
 }
