@@ -347,7 +347,7 @@ int32_t wdg_shell_energy(wdg_ctx* ctx, const wdg_shell* shell, double* out, void
  * The state advances by nsteps steps exactly as with wdg_step (no probe rows).
  * Forward states are checkpointed every checkpoint_interval steps (0:
  * ceil(sqrt(nsteps))); device memory for ceil(nsteps / interval) + 5 interval
- * + 6 state buffers is allocated and freed inside the call.  Needs kappa = 1
+ * + 7 state buffers is allocated and freed inside the call.  Needs kappa = 1
  * and an order and rule with a matrix-core kernel (WDG_EINVAL otherwise: FP64
  * at N = 4, N = 3 with more than 32 cubature points in FP64).  Synchronous. */
 int32_t wdg_loss_gradient(wdg_ctx* ctx, double dt, int32_t nsteps, const wdg_shell* shell,
