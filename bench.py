@@ -13,9 +13,10 @@ in HBM before the timed region starts.  The metric is
 K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
 
 Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`), the
-batching form's throughput (`batch`: 32 independent simulations in one context) and the Table I contrast
+batching form's throughput (`batch`: 32 independent simulations in one context), the Table I contrast
 (`table_i`: memory and time per step of the weight-adjusted, direct stored-matrix and element-constant
-PML schemes, N = 1..4).
+PML schemes, N = 1..4) and the precision form at full size (`precision_form`: 384,000 tets, N = 4, FP64 and
+FP32).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--stepping-only]
                        [--table-i-only] [--copy-calibration MIB]
@@ -218,6 +219,44 @@ def run_batch(steps, warmup, seq_steps=50):
                         "sequential = each simulation in its own context, eager steps, one after another"}
 
 
+def run_precision_form(steps=100, warmup=5):
+    """The precision form at full size: 40^3 x 6 = 384,000 perturbed tets, N = 4 (51-point rule), dipole; element-DOF
+    updates/s in FP64 and FP32 from zero fields, and the FP32 state against the FP64 state after the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_2006_02551_amd import inputs, wdg
+
+    cfg = inputs.config("c3")
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    out, states = {}, {}
+    stream = torch.cuda.current_stream()
+    for prec, name in ((wdg.WDG_FP64, "fp64"), (wdg.WDG_FP32, "fp32")):
+        sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], prec)
+        d = sim.dims
+        sim.set_dipole(cfg["source"])
+        sim.set_fields(np.zeros((d.K, 12, d.Np)))
+        dt = cfg["cfl"] * d.dt_unit
+        sim.step(dt, warmup, stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(dt, steps, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        kernel = "mfma" if sim.dims.kernel == wdg.WDG_KERNEL_MFMA else "scalar"
+        out[name] = {"value": d.K * d.Np / (ms / 1e3), "ms_per_step": ms, "kernel": kernel, "tiles": sim.dims.tiles}
+        states[name] = sim.get_fields()[:, 0:6]
+        del sim
+    out["fp32_rel_l2_vs_fp64"] = float(np.linalg.norm(states["fp32"] - states["fp64"]) / np.linalg.norm(states["fp64"]))
+    out["steps"] = warmup + steps
+    out["workload"] = ("c3: 40^3x6 = 384,000 perturbed tets, N=4 (Np=35), 51-point degree-8 rule, quadratic PML "
+                       "sigma_max=40, dipole, fields from zero")
+    return out
+
+
 def run_table_i(steps=40, warmup=3):
     """The Table I contrast on the GPU: memory and time per step of the weight-adjusted scheme against the
     direct scheme with stored per-element matrices (and element-constant coefficients), N = 1..4, FP64, on
@@ -343,7 +382,7 @@ def main():
           file=sys.stderr, flush=True)
     r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup)
     print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    adj64 = adj32 = batch = table_i = None
+    adj64 = adj32 = batch = table_i = c3 = None
     if not args.stepping_only:
         print("bench: adjoint (loss gradient) against plain stepping, 500 steps, FP64 and FP32", file=sys.stderr,
               flush=True)
@@ -355,6 +394,10 @@ def main():
         print(f"bench: batch {batch['value']:.3e} DOF/s ({batch['speedup_vs_sequential']:.2f}x sequential); "
               f"Table I contrast next", file=sys.stderr, flush=True)
         table_i = run_table_i()
+        print("bench: precision form (c3, 384,000 tets, N=4) FP64 and FP32", file=sys.stderr, flush=True)
+        c3 = run_precision_form()
+        print(f"bench: c3 FP64 {c3['fp64']['value']:.3e} DOF/s, FP32 {c3['fp32']['value']:.3e} DOF/s, "
+              f"FP32 vs FP64 {c3['fp32_rel_l2_vs_fp64']:.1e}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on three steps", file=sys.stderr, flush=True)
@@ -398,6 +441,7 @@ def main():
             "fp32_detail": {k: v for k, v in adj32.items() if k != "ratio"}},
         "batch": batch,
         "table_i": table_i,
+        "precision_form": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
