@@ -38,6 +38,7 @@
 //      update); R -= P_q t1
 //   D. rhs_u = P_q a^-1 V_q R (PML tiles), then the LSERK update.
 #include "device.hpp"
+#include <type_traits>
 
 namespace wdg {
 namespace {
@@ -143,26 +144,49 @@ struct Shape {
     static constexpr int L_SG0 = pad1k(3 * QMAX * T * RB);
     static constexpr int L_GE = pad1k(kGeo * T * RB);
     static constexpr int L_NB = pad1k(NF * T * 4);
-    static constexpr int L_GL = ADJ ? 3 * QMAX * T * RB : 0;  // adjoint: sigma-gradient accumulator
     // The flux buffer holds the face nodes of one round: all of them (one round, two barriers
     // fewer) where that costs no workgroups per compute unit, else the first half.  Where the
     // workgroup would not fit in LDS otherwise, sigma (needed only in the PML phase) is staged into
     // the flux buffer after the flux rounds instead of with the tile.
     static constexpr int L_FL1 = 6 * NF * T * RB, L_FL2 = 6 * 4 * ((SF + 1) / 2) * T * RB;
-    static constexpr int L_NOSG = L_EH + L_GE + L_NB + L_GL;
-    static constexpr bool SG1 = L_FR + TPW * (L_NOSG + L_SG0 + L_FL1) > kLdsCU && L_FL1 >= L_SG0;
-    static constexpr bool SG2 = L_FR + TPW * (L_NOSG + L_SG0 + L_FL2) > kLdsCU && L_FL2 >= L_SG0;
-    static constexpr int LDS1 = L_FR + TPW * (L_NOSG + (SG1 ? 0 : L_SG0) + L_FL1);
-    static constexpr int LDS2 = L_FR + TPW * (L_NOSG + (SG2 ? 0 : L_SG0) + L_FL2);
-    static constexpr bool ONE = LDS1 <= kLdsCU && wg_per_cu(LDS1) == wg_per_cu(LDS2);
+    struct Lay {
+        int lds;
+        bool one, sgfl;
+    };
+    // LDS of the workgroup with a sigma-gradient accumulator of gl bytes per tile; force_sg
+    // stages sigma into the flux buffer wherever it fits there.
+    static constexpr Lay layout(int gl, bool force_sg) {
+        const int nosg = L_EH + L_GE + L_NB + gl;
+        const bool sg1 = (force_sg || L_FR + TPW * (nosg + L_SG0 + L_FL1) > kLdsCU) && L_FL1 >= L_SG0;
+        const bool sg2 = (force_sg || L_FR + TPW * (nosg + L_SG0 + L_FL2) > kLdsCU) && L_FL2 >= L_SG0;
+        const int lds1 = L_FR + TPW * (nosg + (sg1 ? 0 : L_SG0) + L_FL1);
+        const int lds2 = L_FR + TPW * (nosg + (sg2 ? 0 : L_SG0) + L_FL2);
+        const bool one = lds1 <= kLdsCU && wg_per_cu(lds1) == wg_per_cu(lds2);
+        return Lay{one ? lds1 : lds2, one, one ? sg1 : sg2};
+    }
+    // Adjoint: the sigma-gradient accumulator takes LDS atomic adds from all six wavefronts.  A
+    // float LDS atomic add costs about twenty times a double one on gfx950, so the accumulator is
+    // double wherever that keeps the workgroups per compute unit of a float one (sigma moving
+    // into the flux buffer if need be), and float otherwise.
+    static constexpr Lay LAY_R = layout(ADJ ? 3 * QMAX * T * RB : 0, false);
+    static constexpr Lay LAY_D0 = layout(ADJ ? 3 * QMAX * T * 8 : 0, false);
+    static constexpr Lay LAY_D1 = layout(ADJ ? 3 * QMAX * T * 8 : 0, true);
+    static constexpr bool keeps_wg(Lay l) { return l.lds <= kLdsCU && wg_per_cu(l.lds) >= wg_per_cu(LAY_R.lds); }
+    static constexpr int barriers(Lay l) { return (l.one ? 0 : 2) + (l.sgfl ? 1 : 0); }  // beyond the least
+    static constexpr bool D0_OK = keeps_wg(LAY_D0), D1_OK = keeps_wg(LAY_D1);
+    static constexpr Lay LAY_D = D0_OK && (!D1_OK || barriers(LAY_D0) <= barriers(LAY_D1)) ? LAY_D0 : LAY_D1;
+    static constexpr bool GL_D = ADJ && (RB == 8 || D0_OK || D1_OK);
+    static constexpr Lay LAY = (!GL_D || RB == 8) ? LAY_R : LAY_D;
+    static constexpr int L_GL = ADJ ? 3 * QMAX * T * (GL_D ? 8 : RB) : 0;
+    static constexpr bool ONE = LAY.one;
     static constexpr int ROUNDS = ONE ? 1 : 2;
     static constexpr int S0 = ONE ? SF : (SF + 1) / 2;  // k-steps (4 face nodes each) of the first round
     static constexpr int NFH = 4 * S0;  // face nodes per flux round (the second round has NF - NFH)
     static constexpr int L_FL = ONE ? L_FL1 : L_FL2;
-    static constexpr bool SGFL = ONE ? SG1 : SG2;
+    static constexpr bool SGFL = LAY.sgfl;
     static constexpr int L_SG = SGFL ? 0 : L_SG0;
     static constexpr int L_TL = L_EH + L_SG + L_GE + L_NB;
-    static constexpr int LDS = ONE ? LDS1 : LDS2;
+    static constexpr int LDS = LAY.lds;
     // Register budget: as many wavefronts per SIMD as the workgroups that fit
     // in the 160 KiB of LDS of a compute unit bring (at most 6, 80 VGPRs).
     static constexpr int WG_PER_CU = wg_per_cu(LDS);
@@ -199,7 +223,8 @@ void stage_mfma_kernel(StageParams p) {
     __shared__ __attribute__((aligned(16))) char smem[L_FR + TPW * L_TL];
     // flux [component][face node of the round][element of the tile]; sigma rows after the flux when S::SGFL
     __shared__ __attribute__((aligned(16))) real fls[TPW][6 * NFH * T];
-    __shared__ real gls[ADJ ? TPW * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
+    using GR = typename std::conditional<S::GL_D, double, real>::type;  // sigma-gradient accumulator type
+    __shared__ GR gls[ADJ ? TPW * 3 * QMAX * T : 1];  // adjoint: [tile][axis][cubature point][element]
 
     // Workgroup: TPW adjacent tiles of one element block, six
     // wavefronts each (a multiple of four wavefronts keeps the four SIMDs of a
@@ -225,9 +250,9 @@ void stage_mfma_kernel(StageParams p) {
     const int e = T * sub + j;
     const real* __restrict__ qin = static_cast<const real*>(p.q_in);
 
-    real* gl = gls + (ADJ ? h * 3 * QMAX * T : 0);
+    GR* gl = gls + (ADJ ? h * 3 * QMAX * T : 0);
     if constexpr (ADJ) {
-        for (int i = tid; i < 3 * QMAX * T; i += kMfmaThreads) gl[i] = real(0);
+        for (int i = tid; i < 3 * QMAX * T; i += kMfmaThreads) gl[i] = GR(0);
     }
 
     // ---- stage the tile into LDS (direct global->LDS loads)
@@ -488,9 +513,9 @@ void stage_mfma_kernel(StageParams p) {
                         const real gu = -vf * (-vff + (sa - bq) * vpf) - vp * vpf;
                         const real gv = -vf * (vff + (scq - sa) * vpf);
                         const real gw = -vf * (vff + (sbq - sa) * vpf);
-                        atomicAdd(&gl[(ax * QMAX + q) * T + j], w * gu);
-                        atomicAdd(&gl[(bb * QMAX + q) * T + j], w * gv);
-                        atomicAdd(&gl[(cc * QMAX + q) * T + j], w * gw);
+                        atomicAdd(&gl[(ax * QMAX + q) * T + j], static_cast<GR>(w * gu));
+                        atomicAdd(&gl[(bb * QMAX + q) * T + j], static_cast<GR>(w * gv));
+                        atomicAdd(&gl[(cc * QMAX + q) * T + j], static_cast<GR>(w * gw));
                         t1 = kinv * vp - bq * vf;
                         t2 = -cq * vf - dq * vp;
                     } else {

@@ -99,12 +99,17 @@ def test_loss_and_gradient_match_oracle_fp64(wdg, name, over, nsteps):
     assert np.array_equal(sim.get_fields(), sim2.get_fields())
 
 
-def test_loss_and_gradient_fp32_against_fp64_oracle(wdg):
-    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
-    _say("loss gradient fp32")
+@pytest.mark.parametrize("name,over,nsteps", [
+    ("c1", {"mesh.perturb": 0.1, "init.width": 0.35}, 12),
+    ("c2", {"mesh.n": 5, "init": {"component": 2, "center": [0.0] * 3, "width": 0.5}}, 8),
+], ids=["c1", "c2n5"])
+def test_loss_and_gradient_fp32_against_fp64_oracle(wdg, name, over, nsteps):
+    cfg = inputs.config(name, **over)
+    shell = SHELL_C1 if name == "c1" else SHELL_C5
+    _say(f"loss gradient fp32 {name} {over} {nsteps} steps")
     sim, osim, q0 = _pair(wdg, cfg, 1)
-    J, g, gp = sim.loss_gradient(osim.dt, 12, SHELL_C1)
-    Jr, gr, gpr = _oracle_grad(osim, q0, 12, SHELL_C1)
+    J, g, gp = sim.loss_gradient(osim.dt, nsteps, shell)
+    Jr, gr, gpr = _oracle_grad(osim, q0, nsteps, shell)
     err_j, err_g = abs(J - Jr) / Jr, np.max(np.abs(g - gr)) / np.max(np.abs(gr))
     _say(f"  fp32 loss error {err_j:.2e}, gradient error {err_g:.2e}")
     assert err_j <= 1e-5 and err_g <= 2e-4
