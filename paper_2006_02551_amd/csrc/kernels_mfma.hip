@@ -30,8 +30,8 @@
 // 4 g + v for the FP32 MFMA; the host applies the matching permutation.
 //
 // Per PML tile, wavefront u (f = E or H, P its auxiliary field):
-//   B. R = LIFT (Fscale * upwind flux), flux read from LDS in B layout
-//      (after each of the two flux rounds)
+//   B. R += LIFT (Fscale * upwind flux), flux read from LDS in B layout
+//      (after each flux round; after A in forward stages with registers to spare)
 //   C. R += D_r G_r + D_s G_s + D_t G_t, G_d = metric-weighted components
 //   A. VF = V_q f_u, VP = V_q P_u; t1 = b VF + c VP, t2 = kappa^-1 VF - d VP
 //      (eq. (9) at the cubature points); rhs_P = P_q t2 (then its LSERK
@@ -360,9 +360,14 @@ void stage_mfma_kernel(StageParams p) {
     for (int t = 0; t < PT; ++t) R[t] = v4{0, 0, 0, 0};
 
     // ---- upwind flux of all six components (once per tile, shared through
-    // LDS) and B. its lift for component u (eqs. (15)-(17)), in two rounds of
-    // face nodes so that the flux buffer holds half of them
-    {
+    // LDS) and B. its lift for component u (eqs. (15)-(17)), in one or two rounds
+    // of face nodes.  It needs the gathered neighbour traces: in the forward stage,
+    // where registers are to spare (at most four wavefronts per SIMD) and sigma
+    // is not staged into the flux buffer, it runs after the curl and the PML
+    // terms, so that the gathers are in flight behind that matrix work;
+    // elsewhere it runs first.
+    constexpr bool LATE_FLUX = !ADJ && !S::SGFL && S::WAVES_PER_SIMD <= 4;
+    auto flux_and_lift = [&]() {
         const real alpha = static_cast<real>(p.alpha);
 #pragma unroll
         for (int r = 0; r < S::ROUNDS; ++r) {
@@ -406,7 +411,8 @@ void stage_mfma_kernel(StageParams p) {
                 for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L, t, s, SF), b, R[t]);
             }
         }
-    }
+    };
+    if constexpr (!LATE_FLUX) flux_and_lift();
 
     if constexpr (S::SGFL) {
         // every wave has finished reading the flux buffer: stage sigma into it (waited for before A)
@@ -559,6 +565,8 @@ void stage_mfma_kernel(StageParams p) {
                 }
             }
     }
+
+    if constexpr (LATE_FLUX) flux_and_lift();
 
     // ---- dipole source on the electric components (not part of the adjoint operator)
     if (!ADJ && u < 3) {
