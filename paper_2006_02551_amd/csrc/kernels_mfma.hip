@@ -214,6 +214,8 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int Np = S::Np, Nfp = S::Nfp, B = kBlock, T = S::T;
     constexpr int NF = S::NF, PT = S::PT, MR = S::MR, SP = S::SP, SQM = S::SQM, SF = S::SF, S0 = S::S0;
     constexpr bool F64 = sizeof(real) == 8;
+    // flux and lift after the curl and PML terms (forward stages with registers to spare)
+    constexpr bool LATE_FLUX = !ADJ && S::WAVES_PER_SIMD <= 4;
     constexpr int W_D = S::W_D, OFF_VQ = S::OFF_VQ, OFF_PQ = S::OFF_PQ, OFF_D = S::OFF_D, OFF_L = S::OFF_L;
     constexpr int EHS = 6 * Np * B;
     constexpr int NFH = S::NFH;
@@ -265,9 +267,9 @@ void stage_mfma_kernel(StageParams p) {
                    row, T * RB, kGeo, tl + L_EH + L_SG, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(p.nbr + static_cast<size_t>(blk) * NF * B + T * sub), static_cast<size_t>(B) * 4,
                    T * 4, NF, tl + L_EH + L_SG + L_GE, u, 6, lane);
-        if (pml && !S::SGFL)
+        if (pml && (!S::SGFL || LATE_FLUX))
             stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
-                       row, T * RB, 3 * Nq, tl + L_EH, u, 6, lane);
+                       row, T * RB, 3 * Nq, reinterpret_cast<char*>(sgs), u, 6, lane);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -362,11 +364,10 @@ void stage_mfma_kernel(StageParams p) {
     // ---- upwind flux of all six components (once per tile, shared through
     // LDS) and B. its lift for component u (eqs. (15)-(17)), in one or two rounds
     // of face nodes.  It needs the gathered neighbour traces: in the forward stage,
-    // where registers are to spare (at most four wavefronts per SIMD) and sigma
-    // is not staged into the flux buffer, it runs after the curl and the PML
-    // terms, so that the gathers are in flight behind that matrix work;
-    // elsewhere it runs first.
-    constexpr bool LATE_FLUX = !ADJ && !S::SGFL && S::WAVES_PER_SIMD <= 4;
+    // where registers are to spare (at most four wavefronts per SIMD), it runs
+    // after the curl and the PML terms, so that the gathers are in flight behind
+    // that matrix work (sigma, if it lives in the flux buffer, is staged there
+    // with the tile and overwritten by the flux); elsewhere it runs first.
     auto flux_and_lift = [&]() {
         const real alpha = static_cast<real>(p.alpha);
 #pragma unroll
@@ -414,7 +415,7 @@ void stage_mfma_kernel(StageParams p) {
     };
     if constexpr (!LATE_FLUX) flux_and_lift();
 
-    if constexpr (S::SGFL) {
+    if constexpr (S::SGFL && !LATE_FLUX) {
         // every wave has finished reading the flux buffer: stage sigma into it (waited for before A)
         __syncthreads();
         if (pml)
@@ -456,7 +457,7 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
-    if constexpr (S::SGFL) {
+    if constexpr (S::SGFL && !LATE_FLUX) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
@@ -566,7 +567,10 @@ void stage_mfma_kernel(StageParams p) {
             }
     }
 
-    if constexpr (LATE_FLUX) flux_and_lift();
+    if constexpr (LATE_FLUX) {
+        if constexpr (S::SGFL) __syncthreads();  // every wave has read sigma from the flux buffer
+        flux_and_lift();
+    }
 
     // ---- dipole source on the electric components (not part of the adjoint operator)
     if (!ADJ && u < 3) {
