@@ -236,6 +236,7 @@ void stage_mfma_kernel(StageParams p) {
     real* fr = reinterpret_cast<real*>(smem);
     char* tl = smem + L_FR + h * L_TL;
     real* eh = reinterpret_cast<real*>(tl);
+    const real* eh0 = reinterpret_cast<const real*>(smem + L_FR);  // the first tile's E,H rows
     real* sgs = S::SGFL ? fls[h] : reinterpret_cast<real*>(tl + L_EH);
     real* ges = reinterpret_cast<real*>(tl + L_EH + L_SG);
     int* nbs = reinterpret_cast<int*>(tl + L_EH + L_SG + L_GE);
@@ -274,13 +275,14 @@ void stage_mfma_kernel(StageParams p) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- neighbour traces for all flux rounds.  A neighbour inside this tile
-    // (and the own trace at a PEC wall) is read from the staged E,H rows at
-    // flux time (loc >= 0); the others are fetched from global memory now.
+    // ---- neighbour traces for all flux rounds.  A neighbour inside one of the
+    // workgroup's tiles (and the own trace at a PEC wall) is read from the staged
+    // E,H rows at flux time (loc >= 0: offset from the first tile's rows); the
+    // others are fetched from global memory now.
     real nb[S::ROUNDS][FIT][6];
     int loc[S::ROUNDS][FIT], vw[S::ROUNDS][FIT];
     {
-        const int base = blk * EHS + T * sub;
+        const int base = blk * EHS + T * (sub - h);  // the workgroup's first tile
 #pragma unroll
         for (int r = 0; r < S::ROUNDS; ++r)
 #pragma unroll
@@ -291,9 +293,10 @@ void stage_mfma_kernel(StageParams p) {
                 const int vv = nbs[pi];
                 const int off = vv >= 0 ? vv : ~vv;
                 const int rel = off - base;
-                const bool in_tile = static_cast<unsigned>(rel) < static_cast<unsigned>(Np * B) && (rel & (B - 1)) < T;
+                const int el = rel & (B - 1);  // element position within the workgroup's tiles
+                const bool in_tile = static_cast<unsigned>(rel) < static_cast<unsigned>(Np * B) && el < TPW * T;
                 vw[r][it] = vv;
-                loc[r][it] = in_tile ? (rel >> 6) * T + (rel & (B - 1)) : -1;
+                loc[r][it] = in_tile ? (el / T) * (L_TL / RB) + (rel >> 6) * T + (el & (T - 1)) : -1;
                 if (!in_tile) {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) nb[r][it][c] = ldg(qin + c * Np * B, static_cast<unsigned>(off));
@@ -384,7 +387,7 @@ void stage_mfma_kernel(StageParams p) {
                 const int jo = jn * T + jj;
                 real nv[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) nv[c] = loc[r][it] >= 0 ? eh[c * Np * T + loc[r][it]] : nb[r][it][c];
+                for (int c = 0; c < 6; ++c) nv[c] = loc[r][it] >= 0 ? eh0[c * Np * T + loc[r][it]] : nb[r][it][c];
                 const real sE = vw[r][it] >= 0 ? real(1) : real(-1);  // PEC wall: E+ = -E-, H+ = H-
                 const real dEx = eh[0 * Np * T + jo] - sE * nv[0];
                 const real dEy = eh[1 * Np * T + jo] - sE * nv[1];

@@ -21,9 +21,12 @@
 //  * PML elements come first, then interior elements; inside each class the
 //    elements are grouped by face-connected component (numbered in order of
 //    their lowest element index), ordered along a Morton curve of their
-//    centroids within a component, and packed into blocks of B element slots.
-//    A single mesh is one component; a batch of disjoint meshes that overlap
-//    in space keeps each mesh contiguous, so face neighbours stay close.
+//    centroids within a component, regrouped into runs of 16 elements grown
+//    over shared faces (the element tiles of the matrix-core stage kernel, so
+//    that more face neighbours lie in the same tile), and packed into blocks of
+//    B element slots.  A single mesh is one component; a batch of disjoint
+//    meshes that overlap in space keeps each mesh contiguous, so face
+//    neighbours stay close.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -42,6 +45,62 @@ inline void cross3(const double* a, const double* b, double* c) {
 }
 
 const int kFaceVerts[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {0, 2, 3}};
+
+// Regroups an element list (Morton order) into consecutive runs of G elements
+// grown over shared faces: a run starts from the unassigned element with the
+// most faces on the previous run (else the next unassigned element in list
+// order) and repeatedly takes the unassigned face neighbour with the most faces
+// on the run, ties going to the earlier list position.  Only elements of the
+// list are taken.  Returns the new order.
+std::vector<int> grow_runs(const std::vector<int>& order, const std::vector<int>& etoe, int K, int G) {
+    const int n = static_cast<int>(order.size());
+    std::vector<int> pos(K, -1), cnt(K, 0), front, out;
+    std::vector<char> taken(K, 0);
+    std::vector<std::pair<int, int>> carry;  // (element, faces on the previous run)
+    for (int i = 0; i < n; ++i) pos[order[i]] = i;
+    out.reserve(n);
+    int next = 0;  // first list position that may still be unassigned
+    const int64_t nn = n + 1;
+    auto take = [&](int e) {
+        taken[e] = 1;
+        out.push_back(e);
+        for (int f = 0; f < 4; ++f) {
+            const int k2 = etoe[4 * static_cast<size_t>(e) + f];
+            if (k2 != e && pos[k2] >= 0 && !taken[k2] && cnt[k2]++ == 0) front.push_back(k2);
+        }
+    };
+    auto next_unassigned = [&]() {
+        while (taken[order[next]]) ++next;
+        return order[next];
+    };
+    while (static_cast<int>(out.size()) < n) {
+        int seed = -1;
+        int64_t best = -1;
+        for (const auto& ec : carry)
+            if (!taken[ec.first] && static_cast<int64_t>(ec.second) * nn - pos[ec.first] > best) {
+                best = static_cast<int64_t>(ec.second) * nn - pos[ec.first];
+                seed = ec.first;
+            }
+        front.clear();
+        take(seed >= 0 ? seed : next_unassigned());
+        for (int m = 1; m < G && static_cast<int>(out.size()) < n; ++m) {
+            int pick = -1;
+            best = -1;
+            for (const int e : front)
+                if (!taken[e] && static_cast<int64_t>(cnt[e]) * nn - pos[e] > best) {
+                    best = static_cast<int64_t>(cnt[e]) * nn - pos[e];
+                    pick = e;
+                }
+            take(pick >= 0 ? pick : next_unassigned());
+        }
+        carry.clear();
+        for (const int e : front) {
+            if (!taken[e]) carry.push_back({e, cnt[e]});
+            cnt[e] = 0;
+        }
+    }
+    return out;
+}
 
 uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
     x &= 0x1fffff;
@@ -274,7 +333,8 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const i
         S.is_pml[k] = any ? 1 : 0;
     }
 
-    // ---- ordering: PML class first, then component, then Morton order of centroids
+    // ---- ordering: PML class first, then component, then Morton order of centroids, regrouped
+    // into face-grown runs of 16
     std::vector<int> comp(K, -1);
     {
         std::vector<int> stack;
@@ -317,6 +377,11 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const i
     }
     std::sort(pml_list.begin(), pml_list.end());
     std::sort(int_list.begin(), int_list.end());
+    std::vector<int> pml_order, int_order;
+    for (const auto& x : pml_list) pml_order.push_back(x.second);
+    for (const auto& x : int_list) int_order.push_back(x.second);
+    pml_order = grow_runs(pml_order, S.etoe, K, 16);
+    int_order = grow_runs(int_order, S.etoe, K, 16);
     S.K_pml = static_cast<int>(pml_list.size());
     const int B = S.B;
     S.nblk_pml = (S.K_pml + B - 1) / B;
@@ -324,14 +389,14 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const i
     S.nblk = S.nblk_pml + nblk_int;
     S.perm.assign(K, -1);
     S.slot_elem.assign(static_cast<size_t>(S.nblk) * B, -1);
-    for (size_t i = 0; i < pml_list.size(); ++i) {
-        S.perm[pml_list[i].second] = static_cast<int>(i);
-        S.slot_elem[i] = pml_list[i].second;
+    for (size_t i = 0; i < pml_order.size(); ++i) {
+        S.perm[pml_order[i]] = static_cast<int>(i);
+        S.slot_elem[i] = pml_order[i];
     }
-    for (size_t i = 0; i < int_list.size(); ++i) {
+    for (size_t i = 0; i < int_order.size(); ++i) {
         const int slot = S.nblk_pml * B + static_cast<int>(i);
-        S.perm[int_list[i].second] = slot;
-        S.slot_elem[slot] = int_list[i].second;
+        S.perm[int_order[i]] = slot;
+        S.slot_elem[slot] = int_order[i];
     }
     return S;
 }
