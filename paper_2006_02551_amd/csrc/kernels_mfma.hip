@@ -278,9 +278,11 @@ void stage_mfma_kernel(StageParams p) {
     // ---- neighbour traces for all flux rounds.  A neighbour inside one of the
     // workgroup's tiles (and the own trace at a PEC wall) is read from the staged
     // E,H rows at flux time (loc >= 0: offset from the first tile's rows); the
-    // others are fetched from global memory now.
+    // others are gathered from global memory, here when the flux runs first, else
+    // spread over the k-steps of the curl (a gather touches about one cache line
+    // per lane, so a wave issuing them all at once stalls its matrix work).
     real nb[S::ROUNDS][FIT][6];
-    int loc[S::ROUNDS][FIT], vw[S::ROUNDS][FIT];
+    int loc[S::ROUNDS][FIT], vw[S::ROUNDS][FIT], jos[S::ROUNDS][FIT];  // jos: own trace row * T + element
     {
         const int base = blk * EHS + T * (sub - h);  // the workgroup's first tile
 #pragma unroll
@@ -297,7 +299,8 @@ void stage_mfma_kernel(StageParams p) {
                 const bool in_tile = static_cast<unsigned>(rel) < static_cast<unsigned>(Np * B) && el < TPW * T;
                 vw[r][it] = vv;
                 loc[r][it] = in_tile ? (el / T) * (L_TL / RB) + (rel >> 6) * T + (el & (T - 1)) : -1;
-                if (!in_tile) {
+                jos[r][it] = p.fmask[r * NFH + (pi0 < nitem ? pi0 : 0) / T] * T + (pi0 & (T - 1));
+                if (!LATE_FLUX && !in_tile) {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) nb[r][it][c] = ldg(qin + c * Np * B, static_cast<unsigned>(off));
                 }
@@ -383,8 +386,7 @@ void stage_mfma_kernel(StageParams p) {
                 if (pi >= nitem) continue;
                 const int fn = r * NFH + (pi >> 4), jj = pi & 15;
                 const int fc = fn / Nfp;
-                const int jn = p.fmask[fn];
-                const int jo = jn * T + jj;
+                const int jo = jos[r][it];
                 real nv[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) nv[c] = loc[r][it] >= 0 ? eh0[c * Np * T + loc[r][it]] : nb[r][it][c];
@@ -444,8 +446,19 @@ void stage_mfma_kernel(StageParams p) {
         const real rb = sgn * ges[bb * T + j], rc = sgn * ges[cc * T + j];
         const real sb = sgn * ges[(3 + bb) * T + j], sc = sgn * ges[(3 + cc) * T + j];
         const real tb = sgn * ges[(6 + bb) * T + j], tc = sgn * ges[(6 + cc) * T + j];
+        constexpr int NG = S::ROUNDS * FIT * 6, GPS = (NG + SP - 1) / SP;  // gathers, per k-step
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
+            if constexpr (LATE_FLUX) {
+#pragma unroll
+                for (int ig = s * GPS; ig < (s + 1) * GPS && ig < NG; ++ig) {
+                    const int c = ig % 6, it = (ig / 6) % FIT, r = ig / (6 * FIT);
+                    if (loc[r][it] < 0) {
+                        const int vv = vw[r][it], off = vv >= 0 ? vv : ~vv;
+                        nb[r][it][c] = ldg(qin + c * Np * B, static_cast<unsigned>(off));
+                    }
+                }
+            }
             const int node = 4 * s + g;
             const bool ok = (SP * 4 == Np) || node < Np;
             const real xb = ok ? ehv(fo + bb, node) : real(0);
