@@ -31,7 +31,7 @@
 //
 // Per PML tile, wavefront u (f = E or H, P its auxiliary field):
 //   B. R += LIFT (Fscale * upwind flux), flux read from LDS in B layout
-//      (after each flux round; after A in forward stages with registers to spare)
+//      (after each flux round; after A in stages with registers to spare)
 //   C. R += D_r G_r + D_s G_s + D_t G_t, G_d = metric-weighted components
 //   A. VF = V_q f_u, VP = V_q P_u; t1 = b VF + c VP, t2 = kappa^-1 VF - d VP
 //      (eq. (9) at the cubature points); rhs_P = P_q t2 (then its LSERK
@@ -214,8 +214,8 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int Np = S::Np, Nfp = S::Nfp, B = kBlock, T = S::T;
     constexpr int NF = S::NF, PT = S::PT, MR = S::MR, SP = S::SP, SQM = S::SQM, SF = S::SF, S0 = S::S0;
     constexpr bool F64 = sizeof(real) == 8;
-    // flux and lift after the curl and PML terms (forward stages with registers to spare)
-    constexpr bool LATE_FLUX = !ADJ && S::WAVES_PER_SIMD <= 4;
+    // flux and lift after the curl and PML terms (stages with registers to spare; not the FP32 adjoint)
+    constexpr bool LATE_FLUX = (!ADJ || F64) && S::WAVES_PER_SIMD <= 4;
     constexpr int W_D = S::W_D, OFF_VQ = S::OFF_VQ, OFF_PQ = S::OFF_PQ, OFF_D = S::OFF_D, OFF_L = S::OFF_L;
     constexpr int EHS = 6 * Np * B;
     constexpr int NFH = S::NFH;
@@ -380,8 +380,8 @@ void stage_mfma_kernel(StageParams p) {
 
     // ---- upwind flux of all six components (once per tile, shared through
     // LDS) and B. its lift for component u (eqs. (15)-(17)), in one or two rounds
-    // of face nodes.  It needs the gathered neighbour traces: in the forward stage,
-    // where registers are to spare (at most four wavefronts per SIMD), it runs
+    // of face nodes.  It needs the gathered neighbour traces: where registers are
+    // to spare (at most four wavefronts per SIMD; FP32 adjoint excepted), it runs
     // after the curl and the PML terms, so that the gathers are in flight behind
     // that matrix work (sigma, if it lives in the flux buffer, is staged there
     // with the tile and overwritten by the flux); elsewhere it runs first.
