@@ -290,16 +290,24 @@ def run_table_i(steps=40, warmup=3):
         mem = sim.memory_report()
         common = mem["state"] + mem["geometry"] + mem["connectivity"] + mem["operators"]
         row = {"N": N, "Np": d.Np, "Nq": d.Nq, "K": d.K, "K_pml": d.K_pml}
-        t = {"waa": timed(), "waa_kernel": "mfma" if sim.dims.kernel == wdg.WDG_KERNEL_MFMA else "scalar"}
+        default_kernel = sim.dims.kernel
+        # every scheme on the default (matrix-core) kernel, and on the scalar-operand kernel for reference
+        t = {"waa": timed(), "waa_kernel": "mfma" if default_kernel == wdg.WDG_KERNEL_MFMA else "scalar"}
         sim.set_kernel(wdg.WDG_KERNEL_SCALAR)
         t["waa_scalar"] = timed()
+        sim.set_kernel(default_kernel)
         t0 = time.perf_counter()
         sim.set_pml_scheme(wdg.WDG_PML_DIRECT, inputs.product_rule(N + 4))
         row["direct_setup_s"] = time.perf_counter() - t0
         direct_bytes = sim.memory_report()["scheme_data"]
         t["direct"] = timed()
+        sim.set_kernel(wdg.WDG_KERNEL_SCALAR)
+        t["direct_scalar"] = timed()
+        sim.set_kernel(default_kernel)
         sim.set_pml_scheme(wdg.WDG_PML_CONSTANT)
         t["element_constant"] = timed()
+        sim.set_kernel(wdg.WDG_KERNEL_SCALAR)
+        t["element_constant_scalar"] = timed()
         row["ms_per_step"] = t
         row["memory_MB"] = {"waa_total": (common + mem["coefficients"]) / 1e6,
                             "direct_total": (common + direct_bytes) / 1e6,
@@ -307,9 +315,10 @@ def run_table_i(steps=40, warmup=3):
                             "paper_model_waa": mem["paper_waa"] / 1e6, "paper_model_direct": mem["paper_direct"] / 1e6}
         row["direct_over_waa"] = {"memory": row["memory_MB"]["direct_total"] / row["memory_MB"]["waa_total"],
                                   "time": t["direct"] / t["waa"]}
-        print(f"bench: table I N={N}: WAA {t['waa']:.3f} ms/step ({t['waa_kernel']}), direct {t['direct']:.3f}, "
-              f"element-constant {t['element_constant']:.3f}; memory {row['memory_MB']['waa_total']:.0f} vs "
-              f"{row['memory_MB']['direct_total']:.0f} MB", file=sys.stderr, flush=True)
+        print(f"bench: table I N={N} ({t['waa_kernel']} kernel; scalar-operand in brackets): WAA {t['waa']:.3f} "
+              f"({t['waa_scalar']:.3f}) ms/step, direct {t['direct']:.3f} ({t['direct_scalar']:.3f}), element-constant "
+              f"{t['element_constant']:.3f} ({t['element_constant_scalar']:.3f}); memory {row['memory_MB']['waa_total']:.0f} "
+              f"vs {row['memory_MB']['direct_total']:.0f} MB", file=sys.stderr, flush=True)
         rows.append(row)
         del sim
     return {"workload": "t1: 23^3x6 = 73,002 perturbed tets, 52,752 in the PML (Table I: 72,762 / 52,657), cubic "

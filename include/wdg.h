@@ -218,8 +218,9 @@ int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
  *     node farthest beyond the interface along +-u; the weighted mass matrices
  *     are then multiples of M_k and the PML terms are pointwise.
  * Elements carry auxiliary fields on the same set in every scheme (a nonzero
- * sigma or kappa != 1 at a cubature point).  The direct and element-constant
- * schemes run on the scalar-operand kernel. */
+ * sigma or kappa != 1 at a cubature point).  Every scheme runs on the selected
+ * stage kernel (wdg_set_kernel); the direct scheme adds a second launch per
+ * stage that applies the stored products to the PML blocks and updates them. */
 #define WDG_PML_WAA 0
 #define WDG_PML_DIRECT 1
 #define WDG_PML_CONSTANT 2

@@ -256,10 +256,8 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
         const double tt = t - d.t0;
         p.src_g = d.amplitude * std::sin(2.0 * M_PI * d.f0 * tt) * std::exp(-(tt / d.tau) * (tt / d.tau));
     }
-    // the matrix-core kernel implements the weight-adjusted scheme only
-    const int e = (c->kernel == WDG_KERNEL_MFMA && c->pml_scheme == WDG_PML_WAA)
-                      ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, c->tpw, p, stream)
-                      : launch_stage(c->precision, S.ref.N, S.has_kappa, c->pml_scheme, p, stream);
+    const int e = c->kernel == WDG_KERNEL_MFMA ? launch_stage_mfma(c->precision, S.ref.N, S.has_kappa, c->tpw, c->pml_scheme, p, stream)
+                                               : launch_stage(c->precision, S.ref.N, S.has_kappa, c->pml_scheme, p, stream);
     if (e != 0) return fail(c, WDG_EHIP, std::string("stage launch: ") + hipGetErrorString(static_cast<hipError_t>(e)));
     return WDG_OK;
 }
@@ -351,7 +349,7 @@ int32_t wdg_get_dims(const wdg_ctx* c, wdg_dims_t* o) {
     o->dt_unit = S.dt_unit;
     o->time = c->t;
     o->steps = c->steps;
-    o->kernel = c->pml_scheme == WDG_PML_WAA ? c->kernel : WDG_KERNEL_SCALAR;  // the kernel that runs
+    o->kernel = c->kernel;
     o->tiles = c->tpw;
     o->pml_scheme = c->pml_scheme;
     return WDG_OK;

@@ -174,10 +174,8 @@ int32_t wdg_autotune(wdg_ctx* c, int32_t reps, double* times_us, void* hip_strea
         int rc = WDG_OK;
         for (int i = 0; i < 3 && rc == WDG_OK; ++i) {
             double t_us = -1.0;
-            // the matrix-core kernel runs the weight-adjusted scheme only
             if (cands[i].kernel != WDG_KERNEL_MFMA ||
-                (c->mfma_ok && c->pml_scheme == WDG_PML_WAA &&
-                 mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, cands[i].tpw))) {
+                (c->mfma_ok && mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, cands[i].tpw))) {
                 c->kernel = cands[i].kernel;
                 c->tpw = cands[i].tpw;
                 // a stage as in the middle of a step: reads and writes the residual,

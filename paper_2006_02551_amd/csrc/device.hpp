@@ -125,7 +125,10 @@ struct EnergyParams {
 // pml_mode: PmlMode; the direct and element-constant schemes ignore has_kappa (kappa is in their data).
 int launch_stage(int precision, int N, bool has_kappa, int pml_mode, const StageParams& p, hipStream_t s);
 // tpw: 16-element tiles per workgroup of the matrix-core kernel (1 or 2).
-int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s);
+int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, int pml_mode, const StageParams& p, hipStream_t s);
+// The direct scheme's second launch (stored products and update of the PML blocks), after a stage
+// kernel in direct mode has written their vacuum right-hand side to p.pml_work.
+int launch_direct_apply(int precision, int N, const StageParams& p, hipStream_t s);
 // Adjoint stage on the matrix cores (kappa = 1; same (N, N_q) support as the forward).
 int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t s);
 bool mfma_supported(int N, int Nq, int precision);

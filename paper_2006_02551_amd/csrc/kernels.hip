@@ -422,11 +422,16 @@ int launch_stage_t(const StageParams& p, hipStream_t s) {
 }
 
 template <typename real, int N>
-int launch_direct(const StageParams& p, hipStream_t s) {
-    const int e = launch_stage_t<real, N, false, kPmlDirect>(p, s);
-    if (e != 0 || p.nblk_pml == 0) return e;
+int launch_apply(const StageParams& p, hipStream_t s) {
+    if (p.nblk_pml == 0) return 0;
     hipLaunchKernelGGL((direct_apply_kernel<real, N>), dim3(3 * p.nblk_pml), dim3(kApplyWaves * 64), 0, s, p);
     return static_cast<int>(hipGetLastError());
+}
+
+template <typename real, int N>
+int launch_direct(const StageParams& p, hipStream_t s) {
+    const int e = launch_stage_t<real, N, false, kPmlDirect>(p, s);
+    return e != 0 ? e : launch_apply<real, N>(p, s);
 }
 
 template <typename real, int N>
@@ -468,6 +473,20 @@ int launch_energy_t(const EnergyParams& p, double* out, hipStream_t s) {
 int launch_stage(int precision, int N, bool has_kappa, int pml_mode, const StageParams& p, hipStream_t s) {
     return precision == 0 ? launch_stage_r<double>(N, has_kappa, pml_mode, p, s)
                           : launch_stage_r<float>(N, has_kappa, pml_mode, p, s);
+}
+
+int launch_direct_apply(int precision, int N, const StageParams& p, hipStream_t s) {
+    switch (N * 2 + (precision == 0 ? 0 : 1)) {
+        case 2: return launch_apply<double, 1>(p, s);
+        case 3: return launch_apply<float, 1>(p, s);
+        case 4: return launch_apply<double, 2>(p, s);
+        case 5: return launch_apply<float, 2>(p, s);
+        case 6: return launch_apply<double, 3>(p, s);
+        case 7: return launch_apply<float, 3>(p, s);
+        case 8: return launch_apply<double, 4>(p, s);
+        case 9: return launch_apply<float, 4>(p, s);
+        default: return static_cast<int>(hipErrorInvalidValue);
+    }
 }
 
 int launch_probe(int precision, int N, const ProbeParams& p, hipStream_t s) {

@@ -203,10 +203,12 @@ struct Shape {
 //
 // NQ > 0 fixes the number of cubature points at compile time (the stored rules of degree 2N), so that
 // the guards on padded cubature slots resolve at compile time; NQ = 0 reads it from p.Nq.
-template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW, int NQ>
+template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW, int NQ, int MODE = kPmlWaa>
 __global__ __launch_bounds__(TPW * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ, TPW>::WAVES_PER_SIMD)))
 void stage_mfma_kernel(StageParams p) {
     static_assert(!(ADJ && KAPPA), "the adjoint stage is written for kappa = 1");
+    static_assert(MODE == kPmlWaa || (!ADJ && !KAPPA), "the direct and element-constant modes are forward, kappa inside their data");
+    constexpr bool WAA = MODE == kPmlWaa, DIRECT = MODE == kPmlDirect, EC = MODE == kPmlConstant;
     using M = Mma<real>;
     using v4 = typename M::v4;
     using S = Shape<real, N, QT, ADJ, TPW>;
@@ -268,7 +270,7 @@ void stage_mfma_kernel(StageParams p) {
                    row, T * RB, kGeo, tl + L_EH + L_SG, u, 6, lane);
         stage_rows(reinterpret_cast<const char*>(p.nbr + static_cast<size_t>(blk) * NF * B + T * sub), static_cast<size_t>(B) * 4,
                    T * 4, NF, tl + L_EH + L_SG + L_GE, u, 6, lane);
-        if (pml && (!S::SGFL || LATE_FLUX))
+        if (WAA && pml && (!S::SGFL || LATE_FLUX))
             stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
                        row, T * RB, 3 * Nq, reinterpret_cast<char*>(sgs), u, 6, lane);
     }
@@ -325,7 +327,7 @@ void stage_mfma_kernel(StageParams p) {
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
         const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-        bp[s] = pml ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
+        bp[s] = (WAA && pml) ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
     }
     // rows read only by the updates: residuals and update bases (row (kind, t, v) is item
     // (kind PT + t) 4 + v); with the late flux they are issued a few per curl k-step, like the
@@ -341,13 +343,14 @@ void stage_mfma_kernel(StageParams p) {
                 const int nd = node < Np ? node : 0;
                 const unsigned lo = static_cast<unsigned>(j + nd * B);
                 if (s < 0 || ((0 * PT + t) * 4 + v) / UPS == s)
-                    rP[t][v] = (!ADJ && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
+                    rP[t][v] = (!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
                 // (the FP32 adjoint reads its update base where it is used: fewer registers live at
                 // its two-workgroup occupancy)
                 if (s < 0 || ((1 * PT + t) * 4 + v) / UPS == s)
-                    qP[t][v] = ((!ADJ || F64) && pml) ? ldg(qb + pbase, lo) : real(0);
+                    qP[t][v] = ((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0);
                 if (s < 0 || ((2 * PT + t) * 4 + v) / UPS == s)
-                    rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0)) : (read_res ? ldg(rs + ebase, lo) : real(0));
+                    rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0))
+                                   : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, lo) : real(0));
             }
     };
     if constexpr (!LATE_FLUX) load_update_rows(-1);
@@ -434,7 +437,7 @@ void stage_mfma_kernel(StageParams p) {
     if constexpr (S::SGFL && !LATE_FLUX) {
         // every wave has finished reading the flux buffer: stage sigma into it (waited for before A)
         __syncthreads();
-        if (pml)
+        if (WAA && pml)
             stage_rows(reinterpret_cast<const char*>(static_cast<const real*>(p.sigma) + static_cast<size_t>(blk) * 3 * Nq * B + T * sub),
                        static_cast<size_t>(B) * RB, T * RB, 3 * Nq, reinterpret_cast<char*>(fl), u, 6, lane);
     }
@@ -490,8 +493,30 @@ void stage_mfma_kernel(StageParams p) {
         __syncthreads();
     }
 
+    // LSERK update of the auxiliary component from its right-hand side RP
+    auto aux_update = [&](const v4* RP) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int node = 16 * t + 4 * v + g;
+                if (node < Np) {
+                    const unsigned lo = static_cast<unsigned>(j + node * B);
+                    if constexpr (ADJ) {
+                        const real qn = (F64 ? qP[t][v] : ldg(qb + pbase, lo)) + dt * RP[t][v];
+                        stg(qo + pbase, lo, qn);
+                        if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
+                    } else {
+                        const real r = dt * RP[t][v] + rkA * rP[t][v];
+                        stg(rs + pbase, lo, r);
+                        stg(qo + pbase, lo, qP[t][v] + rkB * r);
+                    }
+                }
+            }
+    };
+
     // ---- A. PML terms at the cubature points (eqs. (26)-(29))
-    if (pml) {
+    if (WAA && pml) {
         const real* __restrict__ kp =
             KAPPA ? static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + e : nullptr;
         // One cubature tile (16 points) at a time, so that only its products are live:
@@ -574,25 +599,33 @@ void stage_mfma_kernel(StageParams p) {
                 }
             }
         }
-        // LSERK update of the auxiliary component
+        aux_update(RP);
+    }
+
+    // ---- A'. element-constant scheme: eq. (9) pointwise at the nodes with the element's sigma,
+    // kappa (sampled at its node farthest beyond the interface); rhs = a^-1 (R - b f - c P)
+    real ainv = real(1);
+    if (EC && pml) {
+        const real* __restrict__ ec = static_cast<const real*>(p.pml_mats) + static_cast<size_t>(blk) * 6 * B + e;
+        const real sa = ec[ax * B], sbe = ec[bb * B], sce = ec[cc * B];
+        const real ka = ec[(3 + ax) * B], kb = ec[(3 + bb) * B], kc = ec[(3 + cc) * B];
+        const real kinv = real(1) / ka;
+        const real a = kb * kc * kinv;
+        const real bq = (sbe * kc + sce * kb - a * sa) * kinv;
+        const real cq = sbe * sce - bq * sa;
+        const real dq = sa * kinv;
+        ainv = ka / (kb * kc);
+        v4 RP[PT];
 #pragma unroll
         for (int t = 0; t < PT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int node = 16 * t + 4 * v + g;
-                if (node < Np) {
-                    const unsigned lo = static_cast<unsigned>(j + node * B);
-                    if constexpr (ADJ) {
-                        const real qn = (F64 ? qP[t][v] : ldg(qb + pbase, lo)) + dt * RP[t][v];
-                        stg(qo + pbase, lo, qn);
-                        if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
-                    } else {
-                        const real r = dt * RP[t][v] + rkA * rP[t][v];
-                        stg(rs + pbase, lo, r);
-                        stg(qo + pbase, lo, qP[t][v] + rkB * r);
-                    }
-                }
+                const real f = node < Np ? ehv(u, node) : real(0), P = qP[t][v];
+                R[t][v] -= bq * f + cq * P;
+                RP[t][v] = kinv * f - dq * P;
             }
+        aux_update(RP);
     }
 
     if constexpr (LATE_FLUX) {
@@ -616,10 +649,28 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
+    // ---- direct scheme: the PML tile's vacuum right-hand side goes to the work buffer; its PML
+    // terms and update follow in the apply kernel
+    if (DIRECT && pml) {
+        real* __restrict__ wo = static_cast<real*>(p.pml_work) + static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + e;
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int node = 16 * t + 4 * v + g;
+                if (node < Np) wo[node * B] = R[t][v];
+            }
+        return;
+    }
+    if (EC && pml) {
+#pragma unroll
+        for (int t = 0; t < PT; ++t) R[t] *= ainv;
+    }
+
     // ---- D. weight-adjusted inverse mass on PML tiles: rhs = P_q a^-1 V_q R (eq. (21));
     // in the adjoint it acts before the curl (on y, giving z).  With kappa = 1 and a rule
     // exact to degree 2N it is the identity and is skipped.
-    if (!ADJ && pml && (KAPPA || !p.waa_identity)) {
+    if (!ADJ && WAA && pml && (KAPPA || !p.waa_identity)) {
         v4 Z[QT];
 #pragma unroll
         for (int t = 0; t < QT; ++t) Z[t] = v4{0, 0, 0, 0};
@@ -702,20 +753,20 @@ void stage_mfma_kernel(StageParams p) {
 template <int N>
 constexpr int rule_nq() { return N == 1 ? 4 : N == 2 ? 14 : N == 3 ? 24 : 51; }
 
-template <typename real, int N, int QT, bool K, bool ADJ, int TPW>
+template <typename real, int N, int QT, bool K, bool ADJ, int TPW, int MODE = kPmlWaa>
 int launch_t(const StageParams& p, hipStream_t s) {
     if constexpr (Shape<real, N, QT, ADJ, TPW>::LDS > 160 * 1024) {
         return static_cast<int>(hipErrorInvalidConfiguration);  // more LDS than a compute unit has
     } else {
         const dim3 grid(4 / TPW * p.nblk), block(TPW * kMfmaThreads);
         constexpr int RQ = rule_nq<N>();
-        if constexpr (!K && (RQ + 15) / 16 == QT) {
+        if constexpr (MODE == kPmlWaa && !K && (RQ + 15) / 16 == QT) {
             if (p.Nq == RQ) {
                 hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
                 return static_cast<int>(hipGetLastError());
             }
         }
-        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, 0>), grid, block, 0, s, p);
+        hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, 0, MODE>), grid, block, 0, s, p);
         return static_cast<int>(hipGetLastError());
     }
 }
@@ -724,7 +775,12 @@ template <typename real, int N, int QT>
 constexpr bool adj_fits() { return Shape<real, N, QT, true, 2>::LDS <= 160 * 1024; }
 
 template <typename real, int N, int QT>
-int launch_k(bool k, int tpw, const StageParams& p, hipStream_t s) {
+int launch_k(bool k, int tpw, int mode, const StageParams& p, hipStream_t s) {
+    if (mode == kPmlDirect)
+        return tpw == 1 ? launch_t<real, N, QT, false, false, 1, kPmlDirect>(p, s) : launch_t<real, N, QT, false, false, 2, kPmlDirect>(p, s);
+    if (mode == kPmlConstant)
+        return tpw == 1 ? launch_t<real, N, QT, false, false, 1, kPmlConstant>(p, s)
+                        : launch_t<real, N, QT, false, false, 2, kPmlConstant>(p, s);
     if (tpw == 1) return k ? launch_t<real, N, QT, true, false, 1>(p, s) : launch_t<real, N, QT, false, false, 1>(p, s);
     return k ? launch_t<real, N, QT, true, false, 2>(p, s) : launch_t<real, N, QT, false, false, 2>(p, s);
 }
@@ -745,23 +801,23 @@ int launch_adj(int N, int QT, const StageParams& p, hipStream_t s) {
 // Order / cubature-tile combinations with a matrix-core kernel.  FP64 at
 // N = 4 would need more than the 160 KiB of LDS of a compute unit.
 template <typename real>
-int launch_r(int N, int QT, bool k, int tpw, const StageParams& p, hipStream_t s) {
+int launch_r(int N, int QT, bool k, int tpw, int mode, const StageParams& p, hipStream_t s) {
     switch (N * 10 + QT) {
-        case 11: return launch_k<real, 1, 1>(k, tpw, p, s);
-        case 12: return launch_k<real, 1, 2>(k, tpw, p, s);
-        case 21: return launch_k<real, 2, 1>(k, tpw, p, s);
-        case 22: return launch_k<real, 2, 2>(k, tpw, p, s);
-        case 32: return launch_k<real, 3, 2>(k, tpw, p, s);
-        case 33: return launch_k<real, 3, 3>(k, tpw, p, s);
+        case 11: return launch_k<real, 1, 1>(k, tpw, mode, p, s);
+        case 12: return launch_k<real, 1, 2>(k, tpw, mode, p, s);
+        case 21: return launch_k<real, 2, 1>(k, tpw, mode, p, s);
+        case 22: return launch_k<real, 2, 2>(k, tpw, mode, p, s);
+        case 32: return launch_k<real, 3, 2>(k, tpw, mode, p, s);
+        case 33: return launch_k<real, 3, 3>(k, tpw, mode, p, s);
         default: return -1;
     }
 }
 
 template <typename real>
-int launch_r4(int QT, bool k, int tpw, const StageParams& p, hipStream_t s) {
+int launch_r4(int QT, bool k, int tpw, int mode, const StageParams& p, hipStream_t s) {
     switch (QT) {
-        case 3: return launch_k<real, 4, 3>(k, tpw, p, s);
-        case 4: return launch_k<real, 4, 4>(k, tpw, p, s);
+        case 3: return launch_k<real, 4, 3>(k, tpw, mode, p, s);
+        case 4: return launch_k<real, 4, 4>(k, tpw, mode, p, s);
         default: return -1;
     }
 }
@@ -822,11 +878,16 @@ int launch_adjoint_mfma(int precision, int N, const StageParams& p, hipStream_t 
     return precision == 0 ? launch_adj<double>(N, QT, p, s) : launch_adj<float>(N, QT, p, s);
 }
 
-int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, const StageParams& p, hipStream_t s) {
+int launch_stage_mfma(int precision, int N, bool has_kappa, int tpw, int pml_mode, const StageParams& p, hipStream_t s) {
     const int QT = (p.Nq + 15) / 16;
-    if (N == 4) return precision == 0 ? launch_r4<double>(QT, has_kappa, tpw, p, s) : launch_r4<float>(QT, has_kappa, tpw, p, s);
-    if (precision == 0) return launch_r<double>(N, QT, has_kappa, tpw, p, s);
-    return launch_r<float>(N, QT, has_kappa, tpw, p, s);
+    int e;
+    if (N == 4)
+        e = precision == 0 ? launch_r4<double>(QT, has_kappa, tpw, pml_mode, p, s) : launch_r4<float>(QT, has_kappa, tpw, pml_mode, p, s);
+    else
+        e = precision == 0 ? launch_r<double>(N, QT, has_kappa, tpw, pml_mode, p, s) : launch_r<float>(N, QT, has_kappa, tpw, pml_mode, p, s);
+    // the direct scheme's PML terms and update of the PML blocks
+    if (e == 0 && pml_mode == kPmlDirect) e = launch_direct_apply(precision, N, p, s);
+    return e;
 }
 
 }  // namespace wdg

@@ -5,6 +5,8 @@ the same input rule, `inputs.product_rule(n)` (two rules of equal polynomial deg
 values for the interface-cut elements, whose weights have a kink), and both solve with the resulting
 matrices, so they agree to rounding (1e-11 relative in FP64).
 Element-constant scheme: `oracle.ec` (pointwise closed form).
+Both schemes run on either stage kernel (matrix-core by default, scalar-operand on request); the
+right-hand-side parity cases check both.
 """
 import sys
 
@@ -73,7 +75,7 @@ def test_rhs_parity(wdg, name, over, scheme):
     op = None
     for precision, tol in ((0, 1e-11), (1, 2e-5)):
         sim, vx, ev, rule = _ctx(wdg, cfg, precision, code)
-        assert sim.dims.pml_scheme == code and sim.dims.kernel == wdg.WDG_KERNEL_SCALAR
+        assert sim.dims.pml_scheme == code and sim.dims.kernel == wdg.WDG_KERNEL_MFMA
         if op is None:
             op = _oracle(cfg, vx, ev, rule, scheme)
             q = np.random.default_rng(11).standard_normal((sim.dims.K, 12, sim.dims.Np))
@@ -81,10 +83,12 @@ def test_rhs_parity(wdg, name, over, scheme):
             ref = op.rhs(q, 0.57)
             scale = np.max(np.abs(ref))
         sim.set_fields(q)
-        sim.rhs(0.57)
-        err = np.max(np.abs(sim.get_residual() - ref)) / scale
-        _say(f"  precision {precision}: {err:.2e}")
-        assert err <= tol
+        for kernel in (wdg.WDG_KERNEL_MFMA, wdg.WDG_KERNEL_SCALAR):
+            sim.set_kernel(kernel)
+            sim.rhs(0.57)
+            err = np.max(np.abs(sim.get_residual() - ref)) / scale
+            _say(f"  precision {precision}, kernel {kernel}: {err:.2e}")
+            assert err <= tol
         # the two schemes really differ from the weight-adjusted one on this case
         if precision == 0 and cfg["pml"] is not None:
             sim.set_pml_scheme(wdg.WDG_PML_WAA)
@@ -143,7 +147,7 @@ def test_scheme_data_switching_and_errors(wdg):
         twin.step(dt, 4)
         torch.cuda.synchronize()
         assert np.array_equal(sim.get_fields(), twin.get_fields()), code
-    # back on the weight-adjusted scheme the matrix-core kernel runs again
+    # every scheme runs on the matrix-core kernel by default
     assert sim.dims.kernel == wdg.WDG_KERNEL_MFMA
     fresh = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], 0)
     fresh.set_fields(q)
