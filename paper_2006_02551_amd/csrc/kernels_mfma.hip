@@ -330,8 +330,8 @@ void stage_mfma_kernel(StageParams p) {
         bp[s] = (WAA && pml) ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
     }
     // rows read only by the updates: residuals and update bases (row (kind, t, v) is item
-    // (kind PT + t) 4 + v); with the late flux they are issued a few per curl k-step, like the
-    // gathers: load_update_rows(s) issues the items of k-step s (all of them for s < 0)
+    // (kind PT + t) 4 + v), issued a few per curl k-step (like the gathers of the late flux):
+    // load_update_rows(s) issues the items of k-step s
     constexpr int NU = 3 * PT * 4;
     constexpr int UPS = (NU + SP - 1) / SP;  // update rows per curl k-step
     auto load_update_rows = [&](int s) {
@@ -342,18 +342,17 @@ void stage_mfma_kernel(StageParams p) {
                 const int node = 16 * t + 4 * v + g;
                 const int nd = node < Np ? node : 0;
                 const unsigned lo = static_cast<unsigned>(j + nd * B);
-                if (s < 0 || ((0 * PT + t) * 4 + v) / UPS == s)
+                if (((0 * PT + t) * 4 + v) / UPS == s)
                     rP[t][v] = (!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
                 // (the FP32 adjoint reads its update base where it is used: fewer registers live at
                 // its two-workgroup occupancy)
-                if (s < 0 || ((1 * PT + t) * 4 + v) / UPS == s)
+                if (((1 * PT + t) * 4 + v) / UPS == s)
                     qP[t][v] = ((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0);
-                if (s < 0 || ((2 * PT + t) * 4 + v) / UPS == s)
+                if (((2 * PT + t) * 4 + v) / UPS == s)
                     rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0))
                                    : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, lo) : real(0));
             }
     };
-    if constexpr (!LATE_FLUX) load_update_rows(-1);
     // adjoint: this component's forward fields at the stage input, for the sigma gradient
     constexpr int SPA = ADJ ? SP : 1;
     real ff[SPA], fp[SPA];
@@ -463,8 +462,8 @@ void stage_mfma_kernel(StageParams p) {
         constexpr int NG = S::ROUNDS * FIT * 6, GPS = (NG + SP - 1) / SP;  // gathers, per k-step
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
+            load_update_rows(s);
             if constexpr (LATE_FLUX) {
-                load_update_rows(s);
 #pragma unroll
                 for (int ig = s * GPS; ig < (s + 1) * GPS && ig < NG; ++ig) {
                     const int c = ig % 6, it = (ig / 6) % FIT, r = ig / (6 * FIT);
