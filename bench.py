@@ -358,6 +358,8 @@ def main():
                     help="run the c2 stepping legs only (no adjoint or batch legs), e.g. under a profiler")
     ap.add_argument("--table-i-only", action="store_true",
                     help="run the Table I contrast only and print its JSON (e.g. under a profiler)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run the loss-gradient leg only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (a known-size reference for "
                          "hardware traffic counters)")
@@ -383,6 +385,9 @@ def main():
         del src, dst
     if args.table_i_only:
         print(json.dumps({"table_i": run_table_i()}))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_fp64": run_adjoint(wdg.WDG_FP64), "adjoint_fp32": run_adjoint(wdg.WDG_FP32)}))
         return
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
