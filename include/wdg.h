@@ -188,8 +188,9 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
  * the small dense products are executed.
  *   WDG_KERNEL_SCALAR: one wavefront per field component and 64 elements,
  *     reference operators as scalar FMA operands (any order and rule size);
- *   WDG_KERNEL_MFMA: one wavefront per 16 elements, products on the matrix
- *     cores (the order / cubature sizes listed at wdg_set_kernel).
+ *   WDG_KERNEL_MFMA: six wavefronts (one per field component) per tile of 16
+ *     elements, one or two tiles per workgroup, products on the matrix cores
+ *     (the order / cubature sizes listed at wdg_set_kernel).
  * wdg_create selects MFMA when it is available. */
 #define WDG_KERNEL_AUTO 0
 #define WDG_KERNEL_SCALAR 1
