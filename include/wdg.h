@@ -240,7 +240,8 @@ int32_t wdg_set_pml_scheme(wdg_ctx* ctx, int32_t scheme, int32_t nr, const doubl
 
 /* Tiles of 16 elements per workgroup of the matrix-core kernel: 1 or 2 (the
  * default where two fit in a compute unit's LDS; FP64 at N = 4 takes one,
- * WDG_EINVAL for two).  Results do not depend on it. */
+ * WDG_EINVAL for two).  The per-element arithmetic is the same; the results
+ * agree to rounding (the two are separately compiled kernels). */
 int32_t wdg_set_tiles(wdg_ctx* ctx, int32_t tiles);
 
 /* Times the available stage kernels (scalar-operand; matrix-core with 1 and 2

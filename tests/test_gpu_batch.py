@@ -117,8 +117,10 @@ def test_autotune_and_tile_counts(wdg):
             assert sim.dims.tiles == tiles
             sim.rhs(0.4)
             res[tiles] = sim.get_residual()
-        assert np.array_equal(res[1], res[2])  # element-local arithmetic: the tile count does not matter
         tol = 1e-12 if precision == 0 else 2e-5
+        # element-local arithmetic in the same order: the tile counts agree to rounding (the two are
+        # separately compiled, so contractions into fused multiply-adds may differ)
+        assert np.max(np.abs(res[1] - res[2])) <= (1e-15 if precision == 0 else 1e-6) * np.max(np.abs(ref))
         assert np.max(np.abs(res[1] - ref)) <= tol * np.max(np.abs(ref))
         before = sim.get_fields()
         times = sim.autotune(reps=3)

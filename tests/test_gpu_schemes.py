@@ -149,6 +149,15 @@ def test_scheme_data_switching_and_errors(wdg):
         assert np.array_equal(sim.get_fields(), twin.get_fields()), code
     # every scheme runs on the matrix-core kernel by default
     assert sim.dims.kernel == wdg.WDG_KERNEL_MFMA
+    # the autotuner times both kernels for every scheme and leaves the fields alone
+    for code in (wdg.WDG_PML_DIRECT, wdg.WDG_PML_CONSTANT, wdg.WDG_PML_WAA):
+        sim.set_pml_scheme(code, inputs.product_rule(RULE_N) if code == wdg.WDG_PML_DIRECT else None)
+        before = sim.get_fields()
+        times = sim.autotune(reps=2)
+        assert all(times[k] is not None and times[k] > 0 for k in ("scalar", "mfma_1tile", "mfma_2tiles")), (code, times)
+        assert np.array_equal(sim.get_fields(), before)
+        sim.set_kernel(wdg.WDG_KERNEL_MFMA)
+    sim.set_tiles(2)  # as a fresh context (the tile counts are separately compiled kernels)
     fresh = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], 0)
     fresh.set_fields(q)
     sim.set_fields(q)
