@@ -348,7 +348,7 @@ void stage_mfma_kernel(StageParams p) {
                 // its two-workgroup occupancy)
                 if (((1 * PT + t) * 4 + v) / UPS == s)
                     qP[t][v] = ((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0);
-                if (((2 * PT + t) * 4 + v) / UPS == s)
+                if (!(LATE_FLUX && !ADJ) && ((2 * PT + t) * 4 + v) / UPS == s)  // else issued before the late flux
                     rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0))
                                    : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, lo) : real(0));
             }
@@ -628,6 +628,16 @@ void stage_mfma_kernel(StageParams p) {
     }
 
     if constexpr (LATE_FLUX) {
+        if constexpr (!ADJ) {  // the residual rows of the final update, in flight behind the flux
+#pragma unroll
+            for (int t = 0; t < PT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int node = 16 * t + 4 * v + g;
+                    const int nd = node < Np ? node : 0;
+                    rE[t][v] = (read_res && !(DIRECT && pml)) ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B)) : real(0);
+                }
+        }
         if constexpr (S::SGFL) __syncthreads();  // every wave has read sigma from the flux buffer
         flux_and_lift();
     }
