@@ -149,7 +149,10 @@ const char* wdg_last_error(const wdg_ctx* ctx);
 
 /* Builds the reference operators (eqs. (14)-(21)), geometry, face matching,
  * element classification and device layout; uploads them to the current HIP
- * device unless WDG_HOST_ONLY.  The mesh and method arrays are copied. */
+ * device unless WDG_HOST_ONLY.  The mesh and method arrays are copied.
+ * WDG_EINVAL if the E,H part of the state (nblk x 6 x N_p x 64 words) exceeds
+ * 2^31 - 1 words, the reach of the 32-bit neighbour offsets (about 17.9M
+ * tetrahedra at N = 3, 10.2M at N = 4); a larger mesh is split over devices. */
 int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* method, wdg_ctx** out);
 
 /* Releases everything the library allocated.  Bound state buffers are not freed. */
@@ -158,8 +161,9 @@ void wdg_destroy(wdg_ctx* ctx);
 int32_t wdg_get_dims(const wdg_ctx* ctx, wdg_dims_t* out);
 
 /* Binds three caller-owned device buffers of dims.state_bytes bytes each
- * (two ping-pong field buffers and the Runge-Kutta residual).  They must stay
- * valid until they are rebound or the context is destroyed. */
+ * (two ping-pong field buffers and the Runge-Kutta residual), each 16-byte
+ * aligned (the kernels copy rows with 16-byte loads; WDG_EINVAL otherwise).
+ * They must stay valid until they are rebound or the context is destroyed. */
 int32_t wdg_bind_state(wdg_ctx* ctx, void* q0, void* q1, void* res, int64_t bytes_each);
 
 /* Copies fields in the canonical layout to / from the device (synchronous).
@@ -197,7 +201,10 @@ int32_t wdg_probe_read(wdg_ctx* ctx, double* out, int32_t max_rows, int32_t* nro
 #define WDG_KERNEL_MFMA 2
 
 /* Selects the stage-kernel variant; WDG_EINVAL if MFMA is not available for
- * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64). */
+ * this order and cubature size (N=1,2: N_q <= 32; N=3: 17..48; N=4: 33..64)
+ * or the E,H part of the state is 4 GiB or more (its lanes address neighbour
+ * traces by 32-bit byte offsets: FP64 up to about 4.47M tetrahedra at N = 3,
+ * 2.56M at N = 4, FP32 twice that); WDG_KERNEL_AUTO then takes SCALAR. */
 int32_t wdg_set_kernel(wdg_ctx* ctx, int32_t variant);
 
 /* ---- PML schemes compared with the weight-adjusted one ------------------- */

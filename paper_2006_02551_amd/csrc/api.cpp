@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -56,10 +58,6 @@ int64_t state_index(const Setup& S, int k, int c, int i) {
 }
 
 }  // namespace wdg
-
-namespace {
-
-}  // namespace
 
 namespace wdg {
 
@@ -314,6 +312,9 @@ int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* m, wdg_ctx** out) {
         pp.kappa_max = m->kappa_max;
         ctx->S = build_setup(mesh->nv, mesh->vxyz, mesh->K, mesh->etov, mesh->vertex_id, m->N, m->nq, m->cub_rst,
                              m->cub_w, pp, m->flux_alpha);
+        // neighbour traces are addressed by 32-bit signed word offsets into the E,H part
+        if (static_cast<int64_t>(ctx->S.nblk) * eh_words(ctx->S) > kMaxEhWords)
+            throw Error(WDG_EINVAL, "mesh too large: the E,H part exceeds 2^31 - 1 words (32-bit neighbour offsets)");
         ctx->precision = m->precision;
         ctx->rsize = m->precision == WDG_FP64 ? sizeof(double) : sizeof(float);
         ctx->host_only = (m->flags & WDG_HOST_ONLY) != 0;
@@ -369,6 +370,8 @@ int32_t wdg_bind_state(wdg_ctx* c, void* q0, void* q1, void* res, int64_t bytes_
     if (!c) return WDG_EINVAL;
     if (c->host_only) return fail(c, WDG_ESTATE, "host-only context");
     if (!q0 || !q1 || !res) return fail(c, WDG_EINVAL, "null state buffer");
+    for (const void* b : {static_cast<const void*>(q0), static_cast<const void*>(q1), static_cast<const void*>(res)})
+        if (reinterpret_cast<uintptr_t>(b) % 16 != 0) return fail(c, WDG_EINVAL, "state buffer not 16-byte aligned");
     if (bytes_each < c->state_elems * static_cast<int64_t>(c->rsize)) return fail(c, WDG_EINVAL, "state buffers too small");
     c->q[0] = q0;
     c->q[1] = q1;

@@ -135,6 +135,8 @@ int guarded(wdg_ctx* ctx, F&& fn) {
 }
 
 inline int64_t eh_words(const Setup& S) { return static_cast<int64_t>(6) * S.ref.Np * S.B; }
+// largest E,H part (words) that 32-bit signed neighbour offsets can address
+constexpr int64_t kMaxEhWords = 2147483647;
 
 // Offset of (user element k, canonical component c, node i) in the blocked buffer, or -1.
 int64_t state_index(const Setup& S, int k, int c, int i);

@@ -215,3 +215,11 @@ def test_edge_cases(wdg):
     with pytest.raises(wdg.WdgError) as e:
         sim.energy()
     assert e.value.code == wdg.WDG_ENONFINITE
+    # state buffers must be 16-byte aligned; a refused bind keeps the buffers already bound
+    import ctypes
+    import torch
+    spare = torch.empty(sim.dims.state_bytes + 64, dtype=torch.uint8, device="cuda")
+    p = ctypes.c_void_p(spare.data_ptr() + 8)
+    assert wdg.wdg_bind_state(sim.h, p, p, p, sim.dims.state_bytes) == wdg.WDG_EINVAL
+    assert "aligned" in wdg.wdg_last_error(sim.h).decode()
+    assert np.array_equal(sim.get_fields(), bad, equal_nan=True)
