@@ -218,6 +218,8 @@ void stage_mfma_kernel(StageParams p) {
     constexpr bool F64 = sizeof(real) == 8;
     // flux and lift after the curl and PML terms (stages with registers to spare; not the FP32 adjoint)
     constexpr bool LATE_FLUX = (!ADJ || F64) && S::WAVES_PER_SIMD <= 4;
+    // late flux of the forward weight-adjusted stage: every trace gathered (its long PML phase hides them)
+    constexpr bool GATHER_ALL = LATE_FLUX && !ADJ && WAA;
     constexpr int W_D = S::W_D, OFF_VQ = S::OFF_VQ, OFF_PQ = S::OFF_PQ, OFF_D = S::OFF_D, OFF_L = S::OFF_L;
     constexpr int EHS = 6 * Np * B;
     constexpr int NFH = S::NFH;
@@ -279,10 +281,13 @@ void stage_mfma_kernel(StageParams p) {
 
     // ---- neighbour traces for all flux rounds.  A neighbour inside one of the
     // workgroup's tiles (and the own trace at a PEC wall) is read from the staged
-    // E,H rows at flux time (loc >= 0: offset from the first tile's rows); the
-    // others are gathered from global memory, here when the flux runs first, else
+    // E,H rows at flux time (loc >= 0: offset from the first tile's rows) and the
+    // others are gathered from global memory: here when the flux runs first, else
     // spread over the k-steps of the curl (a gather touches about one cache line
-    // per lane, so a wave issuing them all at once stalls its matrix work).
+    // per lane, so a wave issuing them all at once stalls its matrix work).  With
+    // GATHER_ALL every trace is gathered, the workgroup's own rows from the L2:
+    // unconditional loads let the flux wait for just the loads it reads instead
+    // of every load in flight.
     real nb[S::ROUNDS][FIT][6];
     int loc[S::ROUNDS][FIT], vw[S::ROUNDS][FIT], jos[S::ROUNDS][FIT];  // jos: own trace row * T + element
     {
@@ -402,7 +407,7 @@ void stage_mfma_kernel(StageParams p) {
                 const int jo = jos[r][it];
                 real nv[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) nv[c] = loc[r][it] >= 0 ? eh0[c * Np * T + loc[r][it]] : nb[r][it][c];
+                for (int c = 0; c < 6; ++c) nv[c] = (GATHER_ALL || loc[r][it] < 0) ? nb[r][it][c] : eh0[c * Np * T + loc[r][it]];
                 const real sE = vw[r][it] >= 0 ? real(1) : real(-1);  // PEC wall: E+ = -E-, H+ = H-
                 const real dEx = eh[0 * Np * T + jo] - sE * nv[0];
                 const real dEy = eh[1 * Np * T + jo] - sE * nv[1];
@@ -467,7 +472,7 @@ void stage_mfma_kernel(StageParams p) {
 #pragma unroll
                 for (int ig = s * GPS; ig < (s + 1) * GPS && ig < NG; ++ig) {
                     const int c = ig % 6, it = (ig / 6) % FIT, r = ig / (6 * FIT);
-                    if (loc[r][it] < 0) {
+                    if (GATHER_ALL || loc[r][it] < 0) {
                         const int vv = vw[r][it], off = vv >= 0 ? vv : ~vv;
                         nb[r][it][c] = ldg(qin + c * Np * B, static_cast<unsigned>(off));
                     }
