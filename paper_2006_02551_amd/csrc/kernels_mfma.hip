@@ -218,7 +218,11 @@ void stage_mfma_kernel(StageParams p) {
     constexpr bool F64 = sizeof(real) == 8;
     // flux and lift after the curl and PML terms (stages with registers to spare; not the FP32 adjoint)
     constexpr bool LATE_FLUX = (!ADJ || F64) && S::WAVES_PER_SIMD <= 4;
-    // late flux of the forward weight-adjusted stage: every trace gathered (its long PML phase hides them)
+    // late flux of the forward weight-adjusted stage: every trace gathered (its long PML phase hides
+    // them), and every per-wave row loaded from an address valid in any tile with the stage's
+    // conditions applied where the value is used.  A load under a branch, or a select right after
+    // it, makes the compiler wait for it there, or for every load in flight at the next use of an
+    // earlier one; unconditional loads keep the wait counts exact.
     constexpr bool GATHER_ALL = LATE_FLUX && !ADJ && WAA;
     constexpr int W_D = S::W_D, OFF_VQ = S::OFF_VQ, OFF_PQ = S::OFF_PQ, OFF_D = S::OFF_D, OFF_L = S::OFF_L;
     constexpr int EHS = 6 * Np * B;
@@ -332,11 +336,13 @@ void stage_mfma_kernel(StageParams p) {
     for (int s = 0; s < SP; ++s) {
         const int node = 4 * s + g;
         const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-        bp[s] = (WAA && pml) ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
+        bp[s] = GATHER_ALL ? ldg(pin + (pml ? pbase : ebase), static_cast<unsigned>(j + nd * B))
+                           : ((WAA && pml) ? ldg(pin + pbase, static_cast<unsigned>(j + nd * B)) : real(0));
     }
     // rows read only by the updates: residuals and update bases (row (kind, t, v) is item
     // (kind PT + t) 4 + v), issued a few per curl k-step (like the gathers of the late flux):
-    // load_update_rows(s) issues the items of k-step s
+    // load_update_rows(s) issues the items of k-step s.  With GATHER_ALL a vacuum tile reads its
+    // own E,H rows in place of the auxiliary rows it lacks and never uses the values.
     constexpr int NU = 3 * PT * 4;
     constexpr int UPS = (NU + SP - 1) / SP;  // update rows per curl k-step
     auto load_update_rows = [&](int s) {
@@ -348,11 +354,13 @@ void stage_mfma_kernel(StageParams p) {
                 const int nd = node < Np ? node : 0;
                 const unsigned lo = static_cast<unsigned>(j + nd * B);
                 if (((0 * PT + t) * 4 + v) / UPS == s)
-                    rP[t][v] = (!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0);
+                    rP[t][v] = GATHER_ALL ? ldg(rs + (pml ? pbase : ebase), lo)
+                                          : ((!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0));
                 // (the FP32 adjoint reads its update base where it is used: fewer registers live at
                 // its two-workgroup occupancy)
                 if (((1 * PT + t) * 4 + v) / UPS == s)
-                    qP[t][v] = ((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0);
+                    qP[t][v] = GATHER_ALL ? ldg(qb + (pml ? pbase : ebase), lo)
+                                          : (((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0));
                 if (!(LATE_FLUX && !ADJ) && ((2 * PT + t) * 4 + v) / UPS == s)  // else issued before the late flux
                     rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0))
                                    : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, lo) : real(0));
@@ -511,7 +519,7 @@ void stage_mfma_kernel(StageParams p) {
                         stg(qo + pbase, lo, qn);
                         if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
                     } else {
-                        const real r = dt * RP[t][v] + rkA * rP[t][v];
+                        const real r = dt * RP[t][v] + rkA * ((GATHER_ALL && !read_res) ? real(0) : rP[t][v]);
                         stg(rs + pbase, lo, r);
                         stg(qo + pbase, lo, qP[t][v] + rkB * r);
                     }
@@ -640,7 +648,8 @@ void stage_mfma_kernel(StageParams p) {
                 for (int v = 0; v < 4; ++v) {
                     const int node = 16 * t + 4 * v + g;
                     const int nd = node < Np ? node : 0;
-                    rE[t][v] = (read_res && !(DIRECT && pml)) ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B)) : real(0);
+                    rE[t][v] = GATHER_ALL ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B))
+                                          : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B)) : real(0));
                 }
         }
         if constexpr (S::SGFL) __syncthreads();  // every wave has read sigma from the flux buffer
@@ -742,7 +751,7 @@ void stage_mfma_kernel(StageParams p) {
                     stg(qo + ebase, lo, qn);
                     if (yn) stg(yn + ebase, lo, yna * ehv(u, node) + ynb * qn);
                 } else {
-                    const real r = dt * R[t][v] + rkA * rE[t][v];
+                    const real r = dt * R[t][v] + rkA * ((GATHER_ALL && !read_res) ? real(0) : rE[t][v]);
                     stg(rs + ebase, lo, r);
                     stg(qo + ebase, lo, ehv(u, node) + rkB * r);
                 }
