@@ -223,3 +223,31 @@ def test_edge_cases(wdg):
     assert wdg.wdg_bind_state(sim.h, p, p, p, sim.dims.state_bytes) == wdg.WDG_EINVAL
     assert "aligned" in wdg.wdg_last_error(sim.h).decode()
     assert np.array_equal(sim.get_fields(), bad, equal_nan=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_stale_residual_is_not_read(wdg, precision, kernel):
+    """The first LSERK stage (A_1 = 0) and the right-hand side must not read the residual
+    buffer: NaN left there changes nothing, bitwise (the kernels may load it, but not use it)."""
+    import torch
+    cfg = inputs.config("c1", **{"mesh.n": 2})
+    _say(f"stale residual: precision {precision} kernel {kernel}")
+    clean, osim = _pair(wdg, cfg, precision=precision, init="random", kernel=kernel)
+    dirty, _ = _pair(wdg, cfg, precision=precision, init="random", kernel=kernel)
+    dt = osim.dt
+    for sim in (clean, dirty):
+        sim.rhs(0.0)
+    torch.cuda.synchronize()
+    dirty.bufs[2].fill_(255)  # all-ones bytes: NaN in either precision
+    dirty.rhs(0.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(dirty.get_residual(), clean.get_residual())
+    for sim in (clean, dirty):
+        sim.set_fields(osim.q)
+    dirty.bufs[2].fill_(255)
+    clean.step(dt, 1)
+    dirty.step(dt, 1)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(dirty.get_fields()))
+    assert np.array_equal(dirty.get_fields(), clean.get_fields())
