@@ -360,6 +360,10 @@ def main():
                     help="run the Table I contrast only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run the loss-gradient leg only and print its JSON (e.g. under a profiler)")
+    ap.add_argument("--precision-form-only", action="store_true",
+                    help="run the 384,000-tet N=4 precision-form leg only and print its JSON (e.g. under a profiler)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run the 32-simulation batching leg only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (a known-size reference for "
                          "hardware traffic counters)")
@@ -388,6 +392,12 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_fp64": run_adjoint(wdg.WDG_FP64), "adjoint_fp32": run_adjoint(wdg.WDG_FP32)}))
+        return
+    if args.precision_form_only:
+        print(json.dumps({"precision_form": run_precision_form()}))
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(max(args.steps // 5, 20), 4)}))
         return
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
