@@ -8,9 +8,19 @@ cubic sigma profile (sigma_max = 30), Gaussian-modulated dipole source,
 
 A step is one full LSERK4 step: five launches of the fused stage kernel
 (right-hand side of eqs. (26)-(29) with the upwind curl, the weight-adjusted
-inverse mass and the Runge-Kutta update) plus the probe readout.  Fields live
-in HBM before the timed region starts.  The metric is
-K * N_p * steps / seconds, reported for FP64 (`value`) and FP32 (`fp32`).
+inverse mass P_q a^-1 V_q of eq. (21) applied on every PML element, and the
+Runge-Kutta update) plus the probe readout.  Fields live in HBM before the
+timed region starts.  The metric is K * N_p * steps / seconds, reported for
+FP64 (`value`) and FP32 (`fp32`).  The same stepping with the inverse skipped
+where it is the identity (kappa = 1) is reported separately (`waa_shortcut`).
+
+Roofline: algorithmic bytes and flops per stage launch (see
+`algorithmic_traffic`) over the average launch time of the timed region
+(HIP events on the launch stream; the per-step probe launch is included, so
+the figure is slightly conservative), against the vendor peaks and against
+peaks measured on the same GPU (`measured_peaks`: a 1 GiB device copy and the
+16x16x4 MFMA rate); the bound is whichever of bytes / bandwidth and flops /
+peak is larger.
 
 Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`), the
 batching form's throughput (`batch`: 32 independent simulations in one context), the Table I contrast
@@ -45,7 +55,7 @@ FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)
 
 
-def algorithmic_traffic(d, word: int):
+def algorithmic_traffic(d, word: int, waa_inverse: bool = True):
     """Algorithmic HBM bytes and flops per stage launch, averaged over the five stages.
 
     Per PML element and stage: read q_in (12 N_p words), read the residual
@@ -54,8 +64,12 @@ def algorithmic_traffic(d, word: int):
     geometry (25 words) and the face-node neighbour map (4 N_fp int32).
     Interior elements move the 6 E,H components only and no sigma.
     Neighbour traces are re-reads of q_in (cache traffic, not counted).
-    Flops per PML element (one FMA = 2 flops):
-      volume 3*2*6 N_p^2 + lift 2*6*4 N_fp N_p + PML 6*6*2 N_q N_p + flux ~ 40*4 N_fp;
+    Flops per PML element (one FMA = 2 flops), the products the kernel executes
+    (without the 16-row padding of the matrix-core tiles):
+      volume 3*2*6 N_p^2 + lift 2*6*4 N_fp N_p + flux ~ 40*4 N_fp
+      + PML terms 4*2*6 N_q N_p (V_q f, V_q P, P_q t_2, P_q t_1 per component)
+      + weight-adjusted inverse 2*2*6 N_q N_p (V_q R, P_q Z per component;
+        skipped with the kappa = 1 shortcut);
     interior elements have no PML term.
     """
     Np, Nq, Nfp = d.Np, d.Nq, d.Nfp
@@ -67,8 +81,56 @@ def algorithmic_traffic(d, word: int):
     res_int = 6 * Np * word
     bytes_per_launch = Kp * (fixed_pml + 0.8 * res_pml) + Ki * (fixed_int + 0.8 * res_int)
     fl_common = 36 * Np * Np + 48 * Nfp * Np + 160 * Nfp
-    flops_per_launch = Kp * (fl_common + 72 * Nq * Np) + Ki * fl_common
+    flops_per_launch = Kp * (fl_common + (72 if waa_inverse else 48) * Nq * Np) + Ki * fl_common
     return bytes_per_launch, flops_per_launch
+
+
+def roofline(bytes_per_launch, flops_per_launch, launch_us, word, peaks=None, traffic=None):
+    """Roofline block of one kernel: bound = max(bytes / HBM peak, flops / compute peak of its dtype)."""
+    t = launch_us * 1e-6
+    fpk = FP64_PEAK_TFLOPS if word == 8 else FP32_PEAK_TFLOPS
+    t_hbm, t_flop = bytes_per_launch / (HBM_PEAK_GBS * 1e9), flops_per_launch / (fpk * 1e12)
+    gbs, tfl = bytes_per_launch / t / 1e9, flops_per_launch / t / 1e12
+    if t_hbm >= t_flop:
+        out = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    else:
+        out = {"bound": "mfma", "achieved": tfl, "peak": fpk, "unit": "TFLOP/s", "frac": tfl / fpk}
+    out.update({"traffic": traffic, "bytes_per_launch": bytes_per_launch, "flops_per_launch": flops_per_launch,
+                "launch_us": launch_us, "roofline_us": max(t_hbm, t_flop) * 1e6,
+                "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "achieved_tflops": tfl, "flop_frac": tfl / fpk})
+    if peaks:
+        bw_m = peaks["copy_gbs"]
+        fp_m = peaks["mfma_f64_tflops" if word == 8 else "mfma_f32_tflops"]
+        out["measured_peaks"] = {"hbm_gbs": bw_m, "tflops": fp_m,
+                                 "frac": max(bytes_per_launch / (bw_m * 1e9), flops_per_launch / (fp_m * 1e12)) / t}
+    return out
+
+
+def measured_peaks():
+    """Peaks measured on this GPU: a 1 GiB device-to-device copy (bytes read + written over the time) and the
+    sustained 16x16x4 MFMA rate in FP64 and FP32 (the library's microbenchmark)."""
+    import torch
+
+    from paper_2006_02551_amd import wdg
+
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    reps = 10
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * n * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return {"copy_gbs": copy_gbs, "mfma_f64_tflops": wdg.measure_mfma_peak(wdg.WDG_FP64, 4000),
+            "mfma_f32_tflops": wdg.measure_mfma_peak(wdg.WDG_FP32, 4000),
+            "how": "1 GiB FP32 tensor copy, 10 reps (2 GiB moved each); MFMA 16x16x4 chains, 8 per wavefront, "
+                   "32 wavefronts per compute unit"}
 
 
 def measured_traffic(kernel):
@@ -80,7 +142,7 @@ def measured_traffic(kernel):
     return MEASURED_TRAFFIC.get(kernel)
 
 
-def run_gpu(cfg, precision, steps, warmup):
+def run_gpu(cfg, precision, steps, warmup, shortcut=False, peaks=None):
     import torch
 
     from paper_2006_02551_amd import inputs, wdg
@@ -88,6 +150,7 @@ def run_gpu(cfg, precision, steps, warmup):
     vx, ev = inputs.mesh_for(cfg)
     rule = inputs.load_rule(cfg["cub_degree"])
     sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+    sim.set_waa_shortcut(shortcut)
     d = sim.dims
     q0 = inputs.gaussian_fields(cfg, sim.node_coords())
     sim.set_fields(q0)
@@ -108,19 +171,17 @@ def run_gpu(cfg, precision, steps, warmup):
     e = sim.energy()
     kernel = {wdg.WDG_KERNEL_MFMA: "stage_mfma_kernel", wdg.WDG_KERNEL_SCALAR: "stage_kernel"}[sim.get_dims().kernel]
     word = 8 if precision == wdg.WDG_FP64 else 4
-    b, f = algorithmic_traffic(d, word)
+    b, f = algorithmic_traffic(d, word, waa_inverse=not shortcut)
     launch_ms = ms / (5 * steps)
+    kname = f"{kernel}<{'double' if word == 8 else 'float'},N={d.N},Nq={d.Nq}>"
     out = {
         "value": d.K * d.Np * steps / (ms / 1e3),
         "ms_per_step": ms / steps,
         "stage_launch_us": launch_ms * 1e3,
-        "bytes_per_launch": b,
-        "flops_per_launch": f,
-        "achieved_gbs": b / (launch_ms / 1e3) / 1e9,
-        "achieved_tflops": f / (launch_ms / 1e3) / 1e12,
+        "roofline": roofline(b, f, launch_ms * 1e3, word, peaks, None if shortcut else measured_traffic(kname)),
         "energy": e,
         "probe_rows": int(rows.shape[0]),
-        "kernel": f"{kernel}<{'double' if word == 8 else 'float'},N={d.N},Nq={d.Nq}>",
+        "kernel": kname,
         "dims": {"K": d.K, "K_pml": d.K_pml, "Np": d.Np, "Nq": d.Nq, "nblk": d.nblk, "N": d.N},
     }
     del sim
@@ -219,7 +280,7 @@ def run_batch(steps, warmup, seq_steps=50):
                         "sequential = each simulation in its own context, eager steps, one after another"}
 
 
-def run_precision_form(steps=100, warmup=5):
+def run_precision_form(steps=100, warmup=5, peaks=None):
     """The precision form at full size: 40^3 x 6 = 384,000 perturbed tets, N = 4 (51-point rule), dipole; element-DOF
     updates/s in FP64 and FP32 from zero fields, and the FP32 state against the FP64 state after the timed steps."""
     import numpy as np
@@ -247,7 +308,12 @@ def run_precision_form(steps=100, warmup=5):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
         kernel = "mfma" if sim.dims.kernel == wdg.WDG_KERNEL_MFMA else "scalar"
-        out[name] = {"value": d.K * d.Np / (ms / 1e3), "ms_per_step": ms, "kernel": kernel, "tiles": sim.dims.tiles}
+        word = 8 if prec == wdg.WDG_FP64 else 4
+        kname = (f"{'stage_mfma_kernel' if kernel == 'mfma' else 'stage_kernel'}<{'double' if word == 8 else 'float'},"
+                 f"N={d.N},Nq={d.Nq}>")
+        nb, nf = algorithmic_traffic(d, word)
+        out[name] = {"value": d.K * d.Np / (ms / 1e3), "ms_per_step": ms, "kernel": kernel, "tiles": sim.dims.tiles,
+                     "roofline": roofline(nb, nf, ms * 1e3 / 5, word, peaks, measured_traffic(kname))}
         states[name] = sim.get_fields()[:, 0:6]
         del sim
     out["fp32_rel_l2_vs_fp64"] = float(np.linalg.norm(states["fp32"] - states["fp64"]) / np.linalg.norm(states["fp64"]))
@@ -327,25 +393,49 @@ def run_table_i(steps=40, warmup=3):
             "steps": steps, "rows": rows}
 
 
-def cpu_baseline(cfg, steps=3):
-    """The FP64 oracle on the host cores for a bounded sample (three LSERK4 steps, about 15 s)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, steps=2, par_steps=8, workers=None):
+    """The FP64 oracle on the host cores for a bounded sample: `steps` LSERK4 steps in one process (single-threaded
+    NumPy einsum), then `par_steps` steps with the oracle's right-hand side split over element chunks in
+    `workers` forked processes (the host's CPU share: at most 16)."""
     import numpy as np
 
+    from oracle.pool import ChunkedRHS
     from oracle.run import Simulation as OSim
     from paper_2006_02551_amd import inputs
 
+    workers = workers or min(16, os.cpu_count() or 1)
     vx, ev = inputs.mesh_for(cfg)
     rule = inputs.load_rule(cfg["cub_degree"])
     osim = OSim(cfg, vx, ev, *rule)
     osim.set_state(inputs.gaussian_fields(cfg, osim.mesh.x))
+    K, Np = osim.mesh.K, osim.ref.Np
     t0 = time.perf_counter()
     osim.run(steps)
-    sec = time.perf_counter() - t0
-    K, Np = osim.mesh.K, osim.ref.Np
+    sec1 = time.perf_counter() - t0
+    with ChunkedRHS(osim.op, osim.q.shape, workers) as pool:
+        osim.rhs = pool
+        osim.run(1)  # workers started and warm
+        t0 = time.perf_counter()
+        osim.run(par_steps)
+        secp = time.perf_counter() - t0
     assert np.all(np.isfinite(osim.q))
-    return {"value": K * Np * steps / sec, "unit": "element-DOF updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} LSERK4 step(s) of the 48,000-tet N=3 workload in the NumPy FP64 oracle "
-                      f"({sec:.1f} s; single-threaded einsum; host has {os.cpu_count()} logical CPUs)"}
+    one = K * Np * steps / sec1
+    return {"value": K * Np * par_steps / secp, "unit": "element-DOF updates/s", "cores": workers, "kind": "oracle",
+            "single_thread_value": one, "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "sample": f"the 48,000-tet N=3 workload in the NumPy FP64 oracle: {par_steps} LSERK4 steps with the "
+                      f"right-hand side over {workers} forked processes ({secp:.1f} s), and {steps} steps in one "
+                      f"process, single-threaded ({sec1:.1f} s)"}
 
 
 def main():
@@ -393,19 +483,25 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint_fp64": run_adjoint(wdg.WDG_FP64), "adjoint_fp32": run_adjoint(wdg.WDG_FP32)}))
         return
-    if args.precision_form_only:
-        print(json.dumps({"precision_form": run_precision_form()}))
-        return
     if args.batch_only:
         print(json.dumps({"batch": run_batch(max(args.steps // 5, 20), 4)}))
         return
+    peaks = measured_peaks()
+    print(f"bench: measured peaks: copy {peaks['copy_gbs']:.0f} GB/s, MFMA FP64 {peaks['mfma_f64_tflops']:.1f} "
+          f"TFLOP/s, FP32 {peaks['mfma_f32_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    if args.precision_form_only:
+        print(json.dumps({"precision_form": run_precision_form(peaks=peaks), "measured_peaks": peaks}))
+        return
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
-    r64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup)
+    r64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup, peaks=peaks)
     print(f"bench: FP64 {r64['value']:.3e} DOF/s, {r64['ms_per_step']:.3f} ms/step; FP32 next",
           file=sys.stderr, flush=True)
-    r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup)
-    print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    r32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup, peaks=peaks)
+    print(f"bench: FP32 {r32['value']:.3e} DOF/s, {r32['ms_per_step']:.3f} ms/step; kappa = 1 shortcut next",
+          file=sys.stderr, flush=True)
+    s64 = run_gpu(cfg, wdg.WDG_FP64, args.steps, args.warmup, shortcut=True, peaks=peaks)
+    s32 = run_gpu(cfg, wdg.WDG_FP32, args.steps, args.warmup, shortcut=True, peaks=peaks)
     adj64 = adj32 = batch = table_i = c3 = None
     if not args.stepping_only:
         print("bench: adjoint (loss gradient) against plain stepping, 500 steps, FP64 and FP32", file=sys.stderr,
@@ -419,12 +515,12 @@ def main():
               f"Table I contrast next", file=sys.stderr, flush=True)
         table_i = run_table_i()
         print("bench: precision form (c3, 384,000 tets, N=4) FP64 and FP32", file=sys.stderr, flush=True)
-        c3 = run_precision_form()
+        c3 = run_precision_form(peaks=peaks)
         print(f"bench: c3 FP64 {c3['fp64']['value']:.3e} DOF/s, FP32 {c3['fp32']['value']:.3e} DOF/s, "
               f"FP32 vs FP64 {c3['fp32_rel_l2_vs_fp64']:.1e}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle on three steps", file=sys.stderr, flush=True)
+        print("bench: timing the CPU oracle (one process, then all host cores)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg)
     d = r64["dims"]
     line = {
@@ -441,21 +537,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "c2: 20^3x6=48000 perturbed tets, N=3, Nq=24, cubic PML sigma_max=30, dipole, "
-                               "8 probes, LSERK4", "K": d["K"], "K_pml": d["K_pml"], "N": 3, "Np": d["Np"],
+                               "8 probes, LSERK4; weight-adjusted inverse applied on every PML element",
+                   "K": d["K"], "K_pml": d["K_pml"], "N": 3, "Np": d["Np"],
                    "Nq": d["Nq"], "parallelism": "single GPU"},
+        "roofline": dict(r64["roofline"], kernel=r64["kernel"]),
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32", "kernel": r32["kernel"],
-                 "speedup_vs_fp64": r32["value"] / r64["value"],
-                 "roofline": {"bound": "hbm", "achieved": r32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": r32["achieved_gbs"] / HBM_PEAK_GBS,
-                              "traffic": measured_traffic(r32["kernel"]),
-                              "achieved_tflops": r32["achieved_tflops"],
-                              "flop_frac": r32["achieved_tflops"] / FP32_PEAK_TFLOPS}},
-        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["achieved_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(r64["kernel"]),
-                     "kernel": r64["kernel"], "stage_launch_us": r64["stage_launch_us"],
-                     "bytes_per_launch": r64["bytes_per_launch"],
-                     "achieved_tflops": r64["achieved_tflops"],
-                     "flop_frac": r64["achieved_tflops"] / FP64_PEAK_TFLOPS},
+                 "speedup_vs_fp64": r32["value"] / r64["value"], "roofline": r32["roofline"]},
+        "waa_shortcut": {"what": "the same stepping with P_q a^-1 V_q skipped where it is the identity (kappa = 1)",
+                         "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"],
+                                  "roofline": s64["roofline"]},
+                         "fp32": {"value": s32["value"], "ms_per_step": s32["ms_per_step"],
+                                  "roofline": s32["roofline"]}},
+        "measured_peaks": peaks,
         "adjoint_forward_ratio": None if adj64 is None else {
             "value": adj64["ratio"], "fp32": adj32["ratio"],
             "workload": "c5: the 48,000-tet N=3 mesh, Gaussian Ez pulse, 500 LSERK4 steps, loss = time-integrated "

@@ -266,6 +266,15 @@ int32_t wdg_autotune(wdg_ctx* ctx, int32_t reps, double* times_us, void* hip_str
  * amplitude and the probe row change every step. */
 int32_t wdg_step_graph(wdg_ctx* ctx, double dt, int32_t nsteps, void* hip_stream);
 
+/* The weight-adjusted inverse P_q a^-1 V_q of eq. (21) is applied to every PML
+ * element's right-hand side by default, also where it is the identity: with
+ * kappa = 1 the weight a of eq. (9) is one, and P_q V_q = I for a rule exact to
+ * degree 2N.  on = 1 skips it there (a shortcut, exact to rounding; reported
+ * separately from the default stage); on = 0 restores the default.  WDG_EINVAL
+ * for on = 1 when the product is not the identity (kappa != 1, or
+ * max |P_q V_q - I| >= 1e-12 for the context's rule). */
+int32_t wdg_set_waa_shortcut(wdg_ctx* ctx, int32_t on);
+
 /* Per-element factor on the time step, double [K] in user element order (NULL
  * removes it): element k advances with dt * scale[k], so independent
  * simulations held in one context (disjoint meshes) each keep their own stable
@@ -331,6 +340,17 @@ int32_t wdg_get_sigma_q(const wdg_ctx* ctx, double* sigma);
 /* Physical cubature points double [K][nq][3], user element order. */
 int32_t wdg_cubature_points(const wdg_ctx* ctx, double* xyz);
 
+/* Re-samples sigma at the cubature points from the layer profile of Sec. III,
+ * sigma_u = sigma_max[u] (d_u / L[u])^order, d_u the distance into the layer,
+ * with new parameters (double [3], double [3], double).  The outer wall stays
+ * where creation put it (interface +- thickness) and the interface moves with
+ * L; the values then count as the method's profile again (grad_profile of
+ * wdg_loss_gradient refers to these parameters).  Needs kappa = 1 and the
+ * weight-adjusted scheme (WDG_ESTATE otherwise); WDG_EINVAL for L <= 0,
+ * sigma_max < 0, order < 0, non-finite values, or a layer that would reach
+ * elements created outside it (they carry no auxiliary fields). */
+int32_t wdg_set_pml_profile(wdg_ctx* ctx, const double* sigma_max, const double* L, double order);
+
 /* Axis-aligned shell: the points of the closed box [outer_lo, outer_hi] that
  * are not in the open box (inner_lo, inner_hi). */
 typedef struct wdg_shell {
@@ -352,8 +372,11 @@ int32_t wdg_shell_energy(wdg_ctx* ctx, const wdg_shell* shell, double* out, void
  *   grad_sigma   double [K][nq][3]: dJ/dsigma at the cubature points, zero
  *                outside the PML (NULL: not returned);
  *   grad_profile double [7]: dJ/d(sigma_max x,y,z, L x,y,z, profile order) of
- *                the profile given at creation, with the outer wall fixed and
- *                the interface moving with L (NULL: not returned).
+ *                the profile given at creation or by wdg_set_pml_profile, with
+ *                the outer wall fixed and the interface moving with L (NULL:
+ *                not returned; WDG_ESTATE when sigma was replaced by
+ *                wdg_set_sigma_q or wdg_set_sigma_profile, which no profile
+ *                parameters describe).
  * The state advances by nsteps steps exactly as with wdg_step (no probe rows).
  * Forward states are checkpointed every checkpoint_interval steps (0:
  * ceil(sqrt(nsteps))); device memory for ceil(nsteps / interval) + 5 interval
@@ -363,6 +386,19 @@ int32_t wdg_shell_energy(wdg_ctx* ctx, const wdg_shell* shell, double* out, void
 int32_t wdg_loss_gradient(wdg_ctx* ctx, double dt, int32_t nsteps, const wdg_shell* shell,
                           int32_t checkpoint_interval, double* loss, double* grad_sigma,
                           double* grad_profile, void* hip_stream);
+
+/* ---- Measurement helper --------------------------------------------------- */
+
+/* Sustained rate of the matrix-core instruction the stage kernel uses for its
+ * small dense products (the 16x16x4 FP64 or FP32 MFMA shape), measured on the
+ * current device: eight workgroups of four wavefronts per compute unit, each
+ * wavefront running eight independent accumulator chains of `iters`
+ * instructions; best of three timed launches after one untimed launch.  The roofline's measured compute peak; not part of
+ * the method.  precision WDG_FP64 or WDG_FP32; *tflops receives TFLOP/s (one
+ * multiply-add = 2 flops).  Allocates and frees a small device buffer;
+ * synchronises hip_stream.  WDG_EINVAL for bad arguments, WDG_EHIP on a
+ * launch error. */
+int32_t wdg_measure_mfma_peak(int32_t precision, int32_t iters, void* hip_stream, double* tflops);
 
 #ifdef __cplusplus
 }

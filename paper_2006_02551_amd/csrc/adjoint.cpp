@@ -170,6 +170,43 @@ int32_t wdg_set_sigma_q(wdg_ctx* c, const double* sigma) {
     });
 }
 
+int32_t wdg_set_pml_profile(wdg_ctx* c, const double* sigma_max, const double* L, double order) {
+    if (!c || !sigma_max || !L) return WDG_EINVAL;
+    if (c->S.has_kappa) return fail(c, WDG_ESTATE, "profile parameters are re-sampled for kappa = 1 only");
+    if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_ESTATE, "sigma at the cubature points is used by the weight-adjusted scheme only");
+    if (!(order >= 0.0) || !std::isfinite(order)) return fail(c, WDG_EINVAL, "profile order must be finite and >= 0");
+    for (int d = 0; d < 3; ++d)
+        if (!(L[d] > 0.0) || !(sigma_max[d] >= 0.0) || !std::isfinite(L[d]) || !std::isfinite(sigma_max[d]))
+            return fail(c, WDG_EINVAL, "need L > 0 and sigma_max >= 0, finite");
+    return guarded(c, [&]() -> int {
+        Setup& S = c->S;
+        PmlParams pm = S.pml;
+        for (int d = 0; d < 3; ++d) {
+            const double wall_lo = S.pml.lo[d] - S.pml.L[d], wall_hi = S.pml.hi[d] + S.pml.L[d];
+            pm.lo[d] = wall_lo + L[d];
+            pm.hi[d] = wall_hi - L[d];
+            pm.L[d] = L[d];
+            pm.sigma_max[d] = sigma_max[d];
+        }
+        pm.order = order;
+        const int Nq = S.ref.Nq;
+        std::vector<double> sig(static_cast<size_t>(S.K) * Nq * 3, 0.0);
+        for (int k = 0; k < S.K; ++k)
+            for (int q = 0; q < Nq; ++q)
+                for (int d = 0; d < 3; ++d) {
+                    const size_t i = (static_cast<size_t>(k) * Nq + q) * 3 + d;
+                    sig[i] = pm.sigma_max[d] * profile_ratio(S.xq[i], pm.lo[d], pm.hi[d], pm.L[d], pm.order);
+                    if (sig[i] != 0.0 && !S.is_pml[k])
+                        return fail(c, WDG_EINVAL, "the layer would reach elements created outside it");
+                }
+        S.sigma.swap(sig);
+        S.pml = pm;
+        c->sigma_custom = false;
+        if (!c->host_only) upload_coefficients(c);
+        return WDG_OK;
+    });
+}
+
 int32_t wdg_get_sigma_q(const wdg_ctx* c, double* sigma) {
     if (!c || !sigma) return WDG_EINVAL;
     std::copy(c->S.sigma.begin(), c->S.sigma.end(), sigma);
@@ -208,6 +245,8 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
     if (c->pml_scheme != WDG_PML_WAA) return fail(c, WDG_EINVAL, "the adjoint is built for the weight-adjusted scheme");
     // kappa = 1 and a rule exact to degree 2N (checked at creation) make P_q a^-1 V_q the identity
     if (!c->waa_identity) return fail(c, WDG_EINVAL, "the adjoint needs P_q V_q = I");
+    if (grad_profile && c->sigma_custom)
+        return fail(c, WDG_ESTATE, "sigma was replaced point by point: no profile parameters describe it");
     if (!adjoint_supported(S.ref.N, S.ref.Nq, c->precision))
         return fail(c, WDG_EINVAL, "no adjoint kernel for this order, rule size and precision");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -239,7 +239,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.dt_scale = c->has_dt_scale ? static_cast<const double*>(c->dt_scale.p) : nullptr;
     p.pml_mats = c->pml_mats.p;
     p.pml_work = c->pml_work.p;
-    p.waa_identity = c->waa_identity ? 1 : 0;
+    p.waa_skip = (c->waa_skip && c->waa_identity) ? 1 : 0;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;

@@ -47,6 +47,14 @@ int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
     return WDG_OK;
 }
 
+int32_t wdg_set_waa_shortcut(wdg_ctx* c, int32_t on) {
+    if (!c) return WDG_EINVAL;
+    if (on && !c->waa_identity)
+        return fail(c, WDG_EINVAL, "the weight-adjusted inverse is not the identity here (kappa != 1 or P_q V_q != I)");
+    c->waa_skip = on != 0;
+    return WDG_OK;
+}
+
 int32_t wdg_set_dt_scale(wdg_ctx* c, const double* scale) {
     if (!c) return WDG_EINVAL;
     if (c->host_only) return fail(c, WDG_ESTATE, "host-only context");
@@ -111,7 +119,7 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
         const int pairs = nsteps / 2;
         if (pairs > 0) {
             const bool same = c->graph && c->graph_dt == dt && c->graph_cur == c->cur && c->graph_kernel == c->kernel &&
-                              c->graph_tpw == c->tpw && c->graph_scheme == c->pml_scheme && c->graph_bufs[0] == c->q[0] && c->graph_bufs[1] == c->q[1] &&
+                              c->graph_tpw == c->tpw && c->graph_scheme == c->pml_scheme && c->graph_skip == (c->waa_skip ? 1 : 0) && c->graph_bufs[0] == c->q[0] && c->graph_bufs[1] == c->q[1] &&
                               c->graph_bufs[2] == c->res;
             if (!same) {
                 c->drop_graph();
@@ -141,6 +149,7 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
                 c->graph_cur = c->cur;
                 c->graph_kernel = c->kernel;
                 c->graph_tpw = c->tpw;
+                c->graph_skip = c->waa_skip ? 1 : 0;
                 c->graph_scheme = c->pml_scheme;
                 c->graph_bufs[0] = c->q[0];
                 c->graph_bufs[1] = c->q[1];

@@ -81,6 +81,7 @@ struct wdg_ctx {
     wdg::DevBuf frags;
     bool mfma_ok = false;
     bool waa_identity = false;  // kappa = 1 and P_q V_q = I to rounding
+    bool waa_skip = false;      // skip the weight-adjusted inverse (only where waa_identity holds; opt-in)
     int kernel = WDG_KERNEL_SCALAR;
     int tpw = 2;  // tiles per workgroup of the matrix-core kernel
     // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored
@@ -94,7 +95,7 @@ struct wdg_ctx {
     // captured two-step graph of wdg_step_graph and what it was captured for
     hipGraphExec_t graph = nullptr;
     double graph_dt = 0.0;
-    int graph_cur = -1, graph_kernel = -1, graph_tpw = -1, graph_scheme = -1;
+    int graph_cur = -1, graph_kernel = -1, graph_tpw = -1, graph_scheme = -1, graph_skip = -1;
     void* graph_bufs[3] = {nullptr, nullptr, nullptr};
     ~wdg_ctx() { drop_graph(); }
     // A captured graph holds the device addresses of every buffer a stage reads;

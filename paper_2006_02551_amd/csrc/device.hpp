@@ -83,9 +83,10 @@ struct StageParams {
     const void* pml_mats;    // direct matrices or element-constant coefficients (see the layout above)
     void* pml_work;          // direct scheme: [nblk_pml][6][Np][B] vacuum right-hand side of the PML blocks
     int nblk_pml, nblk, Nq;
-    // 1 when kappa = 1 and P_q V_q = I (a rule exact to degree 2N): a = 1 makes the weight-adjusted
-    // inverse P_q a^-1 V_q the identity, and the kernels skip it
-    int waa_identity;
+    // 1 when the caller asked to skip the weight-adjusted inverse where it is the identity (kappa = 1
+    // and P_q V_q = I, a rule exact to degree 2N: a = 1 makes P_q a^-1 V_q = I); 0 (the default)
+    // applies P_q a^-1 V_q on every PML element
+    int waa_skip;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     double rk_a, rk_b, dt, src_g, alpha;
 };

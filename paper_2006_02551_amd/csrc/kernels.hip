@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
 #pragma unroll
         for (int i = 0; i < Np; ++i) w[i] *= ainv;
     }
-    if (pml && MODE == kPmlWaa && (KAPPA || !p.waa_identity)) {  // the identity when kappa = 1 (see StageParams)
+    if (pml && MODE == kPmlWaa && (KAPPA || !p.waa_skip)) {  // skipped only on request where it is the identity
         real rf[Np];
 #pragma unroll
         for (int i = 0; i < Np; ++i) rf[i] = real(0);

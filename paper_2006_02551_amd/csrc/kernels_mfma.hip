@@ -691,9 +691,9 @@ void stage_mfma_kernel(StageParams p) {
     }
 
     // ---- D. weight-adjusted inverse mass on PML tiles: rhs = P_q a^-1 V_q R (eq. (21));
-    // in the adjoint it acts before the curl (on y, giving z).  With kappa = 1 and a rule
-    // exact to degree 2N it is the identity and is skipped.
-    if (!ADJ && WAA && pml && (KAPPA || !p.waa_identity)) {
+    // in the adjoint it acts before the curl (on y, giving z).  Applied on every PML tile
+    // unless the caller opted out where it is the identity (kappa = 1, rule exact to degree 2N).
+    if (!ADJ && WAA && pml && (KAPPA || !p.waa_skip)) {
         v4 Z[QT];
 #pragma unroll
         for (int t = 0; t < QT; ++t) Z[t] = v4{0, 0, 0, 0};

@@ -111,6 +111,8 @@ wdg_reference_op = _sig("wdg_reference_op", C.c_int32, _ctx, C.c_int32, _dp)
 wdg_element_info = _sig("wdg_element_info", C.c_int32, _ctx, _dp, _dp, _dp, _ip, _ip, _ip)
 wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem_t))
 wdg_set_tiles = _sig("wdg_set_tiles", C.c_int32, _ctx, C.c_int32)
+wdg_set_waa_shortcut = _sig("wdg_set_waa_shortcut", C.c_int32, _ctx, C.c_int32)
+wdg_measure_mfma_peak = _sig("wdg_measure_mfma_peak", C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp)
 wdg_autotune = _sig("wdg_autotune", C.c_int32, _ctx, C.c_int32, _dp, C.c_void_p)
 wdg_step_graph = _sig("wdg_step_graph", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
 wdg_set_dt_scale = _sig("wdg_set_dt_scale", C.c_int32, _ctx, _dp)
@@ -118,6 +120,7 @@ wdg_set_sigma_profile = _sig("wdg_set_sigma_profile", C.c_int32, _ctx, _ip, C.c_
 wdg_set_sigma_q = _sig("wdg_set_sigma_q", C.c_int32, _ctx, _dp)
 wdg_get_sigma_q = _sig("wdg_get_sigma_q", C.c_int32, _ctx, _dp)
 wdg_cubature_points = _sig("wdg_cubature_points", C.c_int32, _ctx, _dp)
+wdg_set_pml_profile = _sig("wdg_set_pml_profile", C.c_int32, _ctx, _dp, _dp, C.c_double)
 wdg_shell_energy = _sig("wdg_shell_energy", C.c_int32, _ctx, C.POINTER(wdg_shell), _dp, C.c_void_p)
 wdg_loss_gradient = _sig("wdg_loss_gradient", C.c_int32, _ctx, C.c_double, C.c_int32, C.POINTER(wdg_shell), C.c_int32,
                          _dp, _dp, _dp, C.c_void_p)
@@ -255,6 +258,12 @@ class Context:
         _check(wdg_get_sigma_q(self.h, _ptr(out)), self.h)
         return out
 
+    def set_pml_profile(self, sigma_max, L, order):
+        """Re-samples sigma at the cubature points from the layer profile with new (sigma_max [3], L [3], order)."""
+        sm = _f64(np.broadcast_to(np.asarray(sigma_max, dtype=np.float64), (3,)))
+        ll = _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+        _check(wdg_set_pml_profile(self.h, _ptr(sm), _ptr(ll), float(order)), self.h)
+
     def set_sigma_q(self, sigma):
         sigma = _f64(sigma)
         d = self.dims
@@ -348,6 +357,10 @@ class Simulation(Context):
         _check(wdg_set_tiles(self.h, int(tiles)), self.h)
         self.dims = self.get_dims()
 
+    def set_waa_shortcut(self, on):
+        """Skip (True) or apply (False, the default) the weight-adjusted inverse where it is the identity."""
+        _check(wdg_set_waa_shortcut(self.h, int(bool(on))), self.h)
+
     def autotune(self, reps=5, stream=None):
         """Times the stage kernels and keeps the fastest; returns us per launch
         {'scalar': t, 'mfma_1tile': t, 'mfma_2tiles': t} (None where unavailable)."""
@@ -378,16 +391,27 @@ class Simulation(Context):
         _check(wdg_shell_energy(self.h, C.byref(sh), C.byref(e), self._stream(stream)), self.h)
         return e.value
 
-    def loss_gradient(self, dt, nsteps, shell, checkpoint_interval=0, stream=None):
-        """(J, dJ/dsigma [K, Nq, 3], dJ/d(sigma_max xyz, L xyz, order) [7]); the state advances nsteps steps."""
+    def loss_gradient(self, dt, nsteps, shell, checkpoint_interval=0, stream=None, profile=True):
+        """(J, dJ/dsigma [K, Nq, 3], dJ/d(sigma_max xyz, L xyz, order) [7] or None when profile is False);
+        the state advances nsteps steps."""
         d = self.dims
         loss = C.c_double(0.0)
         gs = np.zeros((d.K, d.Nq, 3))
-        gp = np.zeros(7)
+        gp = np.zeros(7) if profile else None
         sh = make_shell(shell)
         _check(wdg_loss_gradient(self.h, float(dt), int(nsteps), C.byref(sh), int(checkpoint_interval), C.byref(loss),
-                                 _ptr(gs), _ptr(gp), self._stream(stream)), self.h)
+                                 _ptr(gs), _ptr(gp) if profile else None, self._stream(stream)), self.h)
         return loss.value, gs, gp
+
+
+def measure_mfma_peak(precision, iters=4000, stream=None):
+    """Sustained TFLOP/s of the 16x16x4 MFMA of the given precision on the current device."""
+    out = C.c_double(0.0)
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = wdg_measure_mfma_peak(int(precision), int(iters), st, C.byref(out))
+    if rc != WDG_OK:
+        raise WdgError(rc, f"wdg_measure_mfma_peak failed ({rc})")
+    return out.value
 
 
 def make_shell(shell) -> wdg_shell:
@@ -396,18 +420,6 @@ def make_shell(shell) -> wdg_shell:
         sh.outer_lo[i], sh.outer_hi[i] = float(shell["outer_lo"][i]), float(shell["outer_hi"][i])
         sh.inner_lo[i], sh.inner_hi[i] = float(shell["inner_lo"][i]), float(shell["inner_hi"][i])
     return sh
-
-
-def profile_sigma(xq, sigma_max, L, order, wall_lo, wall_hi):
-    """sigma at points xq [..., 3] (torch) of the profile sigma_max (d / L)^order per axis, where d is
-    the distance into the layer and the layer [wall - L, wall] ends at a fixed outer wall; differentiable
-    in sigma_max [3], L [3] and order (torch tensors)."""
-    lo = torch.as_tensor(wall_lo, dtype=xq.dtype) + L
-    hi = torch.as_tensor(wall_hi, dtype=xq.dtype) - L
-    d = torch.clamp(torch.maximum(xq - hi, lo - xq), min=0.0)
-    inside = d > 0
-    r = torch.where(inside, d / L, torch.ones_like(d))
-    return sigma_max * torch.where(inside, r ** order, torch.zeros_like(d))
 
 
 class ShellLoss(torch.autograd.Function):
@@ -422,9 +434,33 @@ class ShellLoss(torch.autograd.Function):
         sim.set_sigma_q(sigma_q.detach().cpu().numpy())
         sim.set_fields(q0)
         sim.set_time(t0)
-        loss, gs, _ = sim.loss_gradient(dt, nsteps, shell, checkpoint_interval)
+        loss, gs, _ = sim.loss_gradient(dt, nsteps, shell, checkpoint_interval, profile=False)
         ctx.save_for_backward(torch.from_numpy(gs).to(sigma_q.device, sigma_q.dtype))
         return torch.tensor(loss, dtype=sigma_q.dtype, device=sigma_q.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return (gout * g, None, None, None, None, None, None, None)
+
+
+class ProfileLoss(torch.autograd.Function):
+    """Loss sum_{n=1..nsteps} dt E_shell(q_n) as a function of the layer profile theta = (sigma_max x,y,z,
+    L x,y,z, order), a float64 tensor [7].
+
+    forward(theta, sim, q0, t0, dt, nsteps, shell, checkpoint_interval) re-samples sigma on `sim` from theta
+    (outer wall fixed, the interface moving with L), sets the fields q0 and the time t0, runs the library's
+    loss and adjoint sweep once and keeps the library's dJ/dtheta for backward."""
+
+    @staticmethod
+    def forward(ctx, theta, sim, q0, t0, dt, nsteps, shell, checkpoint_interval=0):
+        th = theta.detach().cpu().numpy().astype(np.float64)
+        sim.set_pml_profile(th[0:3], th[3:6], th[6])
+        sim.set_fields(q0)
+        sim.set_time(t0)
+        loss, _, gp = sim.loss_gradient(dt, nsteps, shell, checkpoint_interval)
+        ctx.save_for_backward(torch.from_numpy(gp).to(theta.device, theta.dtype))
+        return torch.tensor(loss, dtype=theta.dtype, device=theta.device)
 
     @staticmethod
     def backward(ctx, gout):

@@ -157,7 +157,7 @@ def test_c5_full_size_gradient_matches_finite_differences(wdg):
         sim.set_sigma_q(sig)
         sim.set_fields(q0)
         sim.set_time(0.0)
-        return sim.loss_gradient(dt, nsteps, shell)[0]
+        return sim.loss_gradient(dt, nsteps, shell, profile=False)[0]
 
     rounding = 100 * np.finfo(float).eps * J
     smax = np.asarray(cfg["pml"]["sigma_max"], float)
@@ -206,24 +206,55 @@ def test_c5_full_size_gradient_matches_finite_differences(wdg):
     sim.set_sigma_q(sig0)
 
 
+def _torch_profile(xq, sigma_max, L, order, wall_lo, wall_hi):
+    """sigma_max (d / L)^order per axis (Sec. III), d the distance into the layer [wall - L, wall] of a fixed
+    outer wall; differentiable in sigma_max [3], L [3] and order (the test's own statement of the profile)."""
+    import torch
+    lo = torch.as_tensor(wall_lo, dtype=xq.dtype) + L
+    hi = torch.as_tensor(wall_hi, dtype=xq.dtype) - L
+    d = torch.clamp(torch.maximum(xq - hi, lo - xq), min=0.0)
+    inside = d > 0
+    r = torch.where(inside, d / L, torch.ones_like(d))
+    return sigma_max * torch.where(inside, r ** order, torch.zeros_like(d))
+
+
 def test_autograd_function_chain_rule(wdg):
+    """The library's profile chain rule (ProfileLoss) against torch's, through the per-node gradient (ShellLoss),
+    at the creation profile and at re-sampled profiles with a moved interface."""
     import torch
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
     _say("torch.autograd.Function")
     sim, osim, q0 = _pair(wdg, cfg, 0)
     pml = cfg["pml"]
     xq = torch.from_numpy(sim.cubature_points())
-    smax = torch.tensor(pml["sigma_max"], dtype=torch.float64, requires_grad=True)
-    L = torch.tensor(pml["L"], dtype=torch.float64, requires_grad=True)
-    order = torch.tensor(float(pml["order"]), dtype=torch.float64, requires_grad=True)
     wall_lo = np.asarray(pml["lo"], float) - np.asarray(pml["L"], float)
     wall_hi = np.asarray(pml["hi"], float) + np.asarray(pml["L"], float)
-    sig = wdg.profile_sigma(xq, smax, L, order, wall_lo, wall_hi)
-    assert np.max(np.abs(sig.detach().numpy() - sim.get_sigma_q())) <= 1e-12 * pml["sigma_max"][0]
-    loss = wdg.ShellLoss.apply(sig, sim, q0, 0.0, osim.dt, 10, SHELL_C1, 0)
-    loss.backward()
-    got = np.concatenate([smax.grad.numpy(), L.grad.numpy(), [order.grad.item()]])
+    for smax0, L0, order0 in ((pml["sigma_max"], pml["L"], pml["order"]),
+                              ([22.0, 18.0, 25.0], [0.45, 0.48, 0.42], 2.5)):
+        smax = torch.tensor(smax0, dtype=torch.float64, requires_grad=True)
+        L = torch.tensor(L0, dtype=torch.float64, requires_grad=True)
+        order = torch.tensor(float(order0), dtype=torch.float64, requires_grad=True)
+        sig = _torch_profile(xq, smax, L, order, wall_lo, wall_hi)
+        loss = wdg.ShellLoss.apply(sig, sim, q0, 0.0, osim.dt, 10, SHELL_C1, 0)
+        loss.backward()
+        want = np.concatenate([smax.grad.numpy(), L.grad.numpy(), [order.grad.item()]])
+        theta = torch.tensor(list(smax0) + list(L0) + [float(order0)], dtype=torch.float64, requires_grad=True)
+        loss2 = wdg.ProfileLoss.apply(theta, sim, q0, 0.0, osim.dt, 10, SHELL_C1, 0)
+        # the library re-sampled the same profile
+        assert np.max(np.abs(sig.detach().numpy() - sim.get_sigma_q())) <= 1e-12 * max(smax0)
+        assert abs(loss2.item() - loss.item()) <= 1e-12 * abs(loss.item())
+        loss2.backward()
+        got = theta.grad.numpy()
+        assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want)), (got, want)
+    # a layer reaching elements created outside it is refused; a point-wise sigma has no profile gradient
+    with pytest.raises(wdg.WdgError) as e:
+        sim.set_pml_profile(pml["sigma_max"], [0.55] * 3, pml["order"])
+    assert e.value.code == wdg.WDG_EINVAL
+    sim.set_sigma_q(sim.get_sigma_q())
     sim.set_fields(q0)
-    sim.set_time(0.0)
-    _, _, gp = sim.loss_gradient(osim.dt, 10, SHELL_C1)
-    assert np.max(np.abs(got - gp)) <= 1e-10 * np.max(np.abs(gp)), (got, gp)
+    with pytest.raises(wdg.WdgError) as e:
+        sim.loss_gradient(osim.dt, 2, SHELL_C1)
+    assert e.value.code == wdg.WDG_ESTATE
+    sim.set_pml_profile(pml["sigma_max"], pml["L"], pml["order"])
+    sim.set_fields(q0)
+    sim.loss_gradient(osim.dt, 2, SHELL_C1)

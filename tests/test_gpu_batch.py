@@ -55,6 +55,35 @@ def test_batch_matches_standalone_runs(wdg, precision):
     assert len(set(np.round(b.dt, 12))) > 1  # the simulations really run at different steps
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_batch_members_match_oracle(wdg, precision, tol):
+    """Each simulation of a stepped batch against the oracle run with its own mesh, profile and time step."""
+    from oracle.run import Simulation as OSim
+    from paper_2006_02551_amd.batch import Batch
+    cfg = inputs.config("c4", batch={"nsim": 4, "n_range": [3, 5], "sigma_range": [10.0, 50.0], "orders": [2, 3, 4],
+                                     "seed": 1})
+    _say(f"batch of 4 against the oracle, precision {precision}")
+    b = Batch(cfg, precision)
+    nsteps = 30
+    q0 = b.initial_fields()
+    b.set_fields(q0)
+    b.step(nsteps, graph=True)
+    q = b.sim.get_fields()
+    for i in range(4):
+        vx, ev = b.meshes[i]
+        ocfg = dict(cfg, pml=b.standalone_pml(i))
+        osim = OSim(ocfg, vx, ev, *b.rule)
+        assert abs(osim.dt - b.dt[i]) <= 1e-14 * osim.dt
+        osim.set_state(inputs.gaussian_fields(ocfg, osim.mesh.x))
+        osim.run(nsteps)
+        got = b.fields(i, q)
+        for sl in (slice(0, 6), slice(6, 12)):
+            err = np.linalg.norm(got[:, sl] - osim.q[:, sl]) / np.linalg.norm(osim.q[:, sl])
+            _say(f"  simulation {i} (K = {osim.mesh.K}, sigma_max {b.recipe[i]['sigma_max']:.1f}, order "
+                 f"{b.recipe[i]['order']}), components {sl.start}..{sl.stop - 1}: relative L2 error {err:.2e}")
+            assert err <= tol
+
+
 def test_graph_replay_matches_eager(wdg):
     import torch
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1})

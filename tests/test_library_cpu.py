@@ -148,6 +148,35 @@ def test_sigma_readout_override_and_cubature_points():
     assert np.array_equal(ctx.get_sigma_q(), new)
 
 
+def test_pml_profile_resampling_matches_oracle():
+    """wdg_set_pml_profile re-samples sigma with new (sigma_max, L, order), the outer wall fixed: the oracle's
+    profile with the interface moved by the change of L gives the same samples."""
+    from oracle.pml import sigma_kappa
+    from oracle.run import Simulation as OSim
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1})
+    ctx, vx, ev, rule = _ctx(cfg)
+    osim = OSim(cfg, vx, ev, *rule)
+    pml = cfg["pml"]
+    smax, L, order = [22.0, 18.0, 25.0], [0.45, 0.48, 0.42], 2.5
+    ctx.set_pml_profile(smax, L, order)
+    wall_lo = np.asarray(pml["lo"]) - np.asarray(pml["L"])
+    wall_hi = np.asarray(pml["hi"]) + np.asarray(pml["L"])
+    moved = dict(pml, lo=list(wall_lo + L), hi=list(wall_hi - np.asarray(L)), L=L, sigma_max=smax, order=order)
+    want, _ = sigma_kappa(osim.op.xq, moved)
+    got = ctx.get_sigma_q()
+    assert np.max(np.abs(got - want)) <= 1e-13 * max(smax)
+    assert np.max(got[~osim.op.is_pml]) == 0.0
+    # the original profile restored exactly
+    ctx.set_pml_profile(pml["sigma_max"], pml["L"], pml["order"])
+    assert np.max(np.abs(ctx.get_sigma_q() - osim.op.sigma)) <= 1e-13 * max(pml["sigma_max"])
+    for bad in (([1.0] * 3, [0.0] * 3, 2.0), ([-1.0] * 3, [0.5] * 3, 2.0), ([1.0] * 3, [0.5] * 3, -1.0),
+                ([1.0] * 3, [0.6] * 3, 2.0)):  # the last reaches elements created outside the layer
+        with pytest.raises(wdg.WdgError) as e:
+            ctx.set_pml_profile(*bad)
+        assert e.value.code == wdg.WDG_EINVAL
+    assert np.max(np.abs(ctx.get_sigma_q() - osim.op.sigma)) <= 1e-13 * max(pml["sigma_max"])
+
+
 def test_loss_gradient_needs_device_state():
     cfg = inputs.config("c1")
     ctx, *_ = _ctx(cfg)
