@@ -259,12 +259,31 @@ int32_t wdg_set_tiles(wdg_ctx* ctx, int32_t tiles);
  * resetting it).  Synchronises hip_stream. */
 int32_t wdg_autotune(wdg_ctx* ctx, int32_t reps, double* times_us, void* hip_stream);
 
+/* Like wdg_autotune, through a cache of chosen variants keyed by device
+ * architecture, order, rule size, precision, PML scheme, kappa and the mesh's
+ * size class (blocks rounded up to a power of two): a cached choice is applied
+ * without timing (*from_cache = 1, may be NULL), otherwise the variants are
+ * timed over `reps` launches and the choice is stored (*from_cache = 0).  The
+ * cache lives in the process; when the environment variable
+ * WDG_AUTOTUNE_CACHE names a file, entries are also read from it and appended
+ * to it.  At creation the environment variables WDG_KERNEL (scalar | mfma)
+ * and WDG_TILES (1 | 2) override the default variant (WDG_EINVAL from
+ * wdg_create for other values or an unavailable choice). */
+int32_t wdg_autotune_cached(wdg_ctx* ctx, int32_t reps, void* hip_stream, int32_t* from_cache);
+
 /* Advances nsteps steps like wdg_step by replaying a captured HIP graph of two
  * steps (ten stage launches), re-captured when dt, the kernel choice or the
  * bound buffers change; an odd last step is launched directly.  Needs a
  * non-NULL stream, no dipole source and no probes (WDG_EINVAL): the source
  * amplitude and the probe row change every step. */
 int32_t wdg_step_graph(wdg_ctx* ctx, double dt, int32_t nsteps, void* hip_stream);
+
+/* Order in which workgroups take the element tiles (blocks) of a stage launch:
+ * 0 natural (default), 1 reversed.  Every element's stage arithmetic reads
+ * only q_in and writes only its own rows of q_out and the residual (ping-pong
+ * buffers), so the results must be bitwise identical in either order: a
+ * check for cross-element read-after-write hazards.  WDG_EINVAL otherwise. */
+int32_t wdg_set_schedule(wdg_ctx* ctx, int32_t reversed);
 
 /* The weight-adjusted inverse P_q a^-1 V_q of eq. (21) is applied to every PML
  * element's right-hand side by default, also where it is the identity: with

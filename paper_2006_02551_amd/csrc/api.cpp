@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <memory>
@@ -172,9 +173,16 @@ void upload_setup(wdg_ctx* c) {
         std::vector<double> fr;
         auto add = [&](const Mat& X, int rows, int cols, int tiles, int ksteps, bool compact) {
             const size_t start = fr.size();
+            auto val = [&](int row, int col) { return row < rows && col < cols ? X[static_cast<size_t>(row) * cols + col] : 0.0; };
             for (int t = 0; t < tiles; ++t)
                 for (int ks = 0; ks < ksteps; ++ks) {
-                    if (compact && t == tiles - 1) {
+                    if (f64) {
+                        // four-block 4x4x4 products: word (k, i, v) holds row 16 t + 4 v + i, column 4 ks + k
+                        const int nv = (compact && t == tiles - 1) ? (rows - 16 * t + 3) / 4 : 4;
+                        for (int k = 0; k < 4; ++k)
+                            for (int i = 0; i < 4; ++i)
+                                for (int v = 0; v < nv; ++v) fr.push_back(val(16 * t + 4 * v + i, 4 * ks + k));
+                    } else if (compact && t == tiles - 1) {
                         const int m = rows - 16 * t;
                         for (int k = 0; k < 4; ++k)
                             for (int i = 0; i < m; ++i) {
@@ -188,7 +196,7 @@ void upload_setup(wdg_ctx* c) {
                         }
                     }
                 }
-            if (fr.size() - start != static_cast<size_t>(frag_words(rows, tiles, ksteps, compact)))
+            if (fr.size() - start != static_cast<size_t>(frag_words(rows, tiles, ksteps, compact, f64)))
                 throw std::logic_error("fragment size");
         };
         add(R.Vq, Nq, Np, QT, SP, false);
@@ -201,6 +209,21 @@ void upload_setup(wdg_ctx* c) {
         fr.resize(static_cast<size_t>(frag_chunks(static_cast<int>(fr.size()), static_cast<int>(c->rsize))) * 1024 / c->rsize, 0.0);
         c->frags.upload(to_real(fr, c->precision).data(), fr.size() * c->rsize);
         c->kernel = WDG_KERNEL_MFMA;
+    }
+    // environment overrides of the stage-kernel choice (checked like wdg_set_kernel / wdg_set_tiles)
+    if (const char* k = std::getenv("WDG_KERNEL")) {
+        if (std::strcmp(k, "scalar") == 0)
+            c->kernel = WDG_KERNEL_SCALAR;
+        else if (std::strcmp(k, "mfma") == 0 && c->mfma_ok)
+            c->kernel = WDG_KERNEL_MFMA;
+        else
+            throw Error(WDG_EINVAL, std::string("WDG_KERNEL=") + k + ": expected scalar, or mfma where available");
+    }
+    if (const char* t = std::getenv("WDG_TILES")) {
+        const int tiles = std::strcmp(t, "1") == 0 ? 1 : std::strcmp(t, "2") == 0 ? 2 : 0;
+        if (tiles == 0 || (c->mfma_ok && !mfma_tiles_fit(R.N, Nq, c->precision, tiles)))
+            throw Error(WDG_EINVAL, std::string("WDG_TILES=") + t + ": expected 1 or 2 tiles that fit in a compute unit");
+        c->tpw = tiles;
     }
     c->fmask.upload(R.fmask.data(), R.fmask.size() * sizeof(int));
     c->cubw.upload(R.wq.data(), R.wq.size() * sizeof(double));
@@ -244,6 +267,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.nblk = S.nblk;
     p.Nq = S.ref.Nq;
     p.read_res = read_res ? 1 : 0;
+    p.order_rev = c->order_rev ? 1 : 0;
     p.rk_a = rk_a;
     p.rk_b = rk_b;
     p.dt = dt;

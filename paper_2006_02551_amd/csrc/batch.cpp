@@ -11,7 +11,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "context.hpp"
@@ -34,9 +41,82 @@ int launch_steps(wdg_ctx* c, double dt, int nsteps, hipStream_t s) {
     return WDG_OK;
 }
 
+// Autotune cache: the chosen (kernel, tiles) per device architecture, order, rule size, precision, PML
+// scheme, kappa and mesh size class (blocks rounded to a power of two), in this process and, when the
+// environment variable WDG_AUTOTUNE_CACHE names a file, in that file (one "key kernel tiles" line per
+// entry, appended as entries are made).
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const wdg_ctx* c) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    int cls = 0;
+    while ((1 << cls) < c->S.nblk) ++cls;
+    std::ostringstream k;
+    k << arch << "/N" << c->S.ref.N << "/q" << c->S.ref.Nq << "/" << (c->precision == WDG_FP64 ? "f64" : "f32") << "/s"
+      << c->pml_scheme << "/k" << (c->S.has_kappa ? 1 : 0) << "/b" << cls;
+    return k.str();
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("WDG_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string key;
+    int kernel = 0, tiles = 0;
+    while (f >> key >> kernel >> tiles)
+        if ((kernel == WDG_KERNEL_SCALAR || kernel == WDG_KERNEL_MFMA) && (tiles == 1 || tiles == 2)) g_tune[key] = {kernel, tiles};
+}
+
+void tune_store_locked(const std::string& key, int kernel, int tiles) {
+    g_tune[key] = {kernel, tiles};
+    const char* path = std::getenv("WDG_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << kernel << " " << tiles << "\n";
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t wdg_autotune_cached(wdg_ctx* c, int32_t reps, void* hip_stream, int32_t* from_cache) {
+    if (!c || reps < 1) return WDG_EINVAL;
+    if (int e = check_state(c)) return e;
+    const std::string key = tune_key(c);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_load_locked();
+        const auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            const int kernel = it->second.first, tiles = it->second.second;
+            const bool ok = kernel == WDG_KERNEL_SCALAR ||
+                            (c->mfma_ok && mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, tiles));
+            if (ok) {
+                c->kernel = kernel;
+                c->tpw = kernel == WDG_KERNEL_MFMA ? tiles : c->tpw;
+                c->drop_graph();
+                if (from_cache) *from_cache = 1;
+                return WDG_OK;
+            }
+        }
+    }
+    const int rc = wdg_autotune(c, reps, nullptr, hip_stream);
+    if (rc != WDG_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_store_locked(key, c->kernel, c->tpw);
+    }
+    if (from_cache) *from_cache = 0;
+    return WDG_OK;
+}
 
 int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
     if (!c) return WDG_EINVAL;
@@ -44,6 +124,13 @@ int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
     if (c->mfma_ok && !mfma_tiles_fit(c->S.ref.N, c->S.ref.Nq, c->precision, tiles))
         return fail(c, WDG_EINVAL, "this many tiles per workgroup need more LDS than a compute unit has");
     c->tpw = tiles;
+    return WDG_OK;
+}
+
+int32_t wdg_set_schedule(wdg_ctx* c, int32_t reversed) {
+    if (!c || (reversed != 0 && reversed != 1)) return WDG_EINVAL;
+    c->drop_graph();
+    c->order_rev = reversed != 0;
     return WDG_OK;
 }
 

@@ -82,6 +82,7 @@ struct wdg_ctx {
     bool mfma_ok = false;
     bool waa_identity = false;  // kappa = 1 and P_q V_q = I to rounding
     bool waa_skip = false;      // skip the weight-adjusted inverse (only where waa_identity holds; opt-in)
+    bool order_rev = false;     // workgroups take tiles in reversed order (schedule-permutation check)
     int kernel = WDG_KERNEL_SCALAR;
     int tpw = 2;  // tiles per workgroup of the matrix-core kernel
     // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored

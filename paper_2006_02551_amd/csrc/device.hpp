@@ -36,16 +36,24 @@ constexpr int kDirectMats = 5;  // stored products per element and axis
 
 // MFMA operand fragments.  An operator with `rows` rows is cut into tiles of
 // 16 rows; for every tile t and k-step s (4 columns) there is one fragment.
-// A full tile's fragment is 64 words, lane l holding
-//   Op[16 t + qloc(l % 16)][4 s + l / 16],
-// where qloc(r) = r for the FP64 MFMA and 4 (r % 4) + r / 4 for the FP32 MFMA
-// (so that register v of lane group g of a product holds row 16 t + 4 v + g).
-// When an operator is stored compact, its last tile keeps only its m valid
-// rows: 4 m words Op[16 t + i][4 s + k] at k m + i, and lane l reads word
-// (l / 16) m + min(qloc(l % 16), m - 1) (rows past m repeat a valid row; the
-// kernels never use those output rows).
-constexpr int frag_words(int rows, int tiles, int ksteps, bool compact) {
-    return compact ? ((tiles - 1) * 64 + 4 * (rows - 16 * (tiles - 1))) * ksteps : tiles * 64 * ksteps;
+//
+// FP32 (16x16x4 product): a full tile's fragment is 64 words, lane l holding
+//   Op[16 t + 4 (r % 4) + r / 4][4 s + l / 16],  r = l % 16,
+// so that register v of lane group g of a product holds row 16 t + 4 v + g.
+// Stored compact, the last tile keeps only its m valid rows: 4 m words
+// Op[16 t + i][4 s + k] at k m + i; lane l reads word (l / 16) m + min(i, m - 1)
+// (rows past m repeat a valid row; the kernels never use those output rows).
+//
+// FP64 (four-block 4x4x4 products, one per result register v = rows 4v..4v+3
+// of the tile): a full tile's fragment is 64 words, word 16 k + 4 i + v holding
+//   Op[16 t + 4 v + i][4 s + k];
+// lane l = 16 k + 4 b + i (b = column block) reads the four words 16 k + 4 i + v.
+// Stored compact, the last tile keeps only its nv = ceil(m / 4) leading
+// registers: 16 nv words, word 4 nv k + nv i + v (rows past m are zero).
+constexpr int frag_words(int rows, int tiles, int ksteps, bool compact, bool f64) {
+    const int m = rows - 16 * (tiles - 1);
+    const int last = f64 ? 16 * ((m + 3) / 4) : 4 * m;
+    return compact ? ((tiles - 1) * 64 + last) * ksteps : tiles * 64 * ksteps;
 }
 // Number of 1 KiB chunks that hold nwords fragment words.
 constexpr int frag_chunks(int nwords, int word_bytes) { return (nwords * word_bytes + 1023) / 1024; }
@@ -88,6 +96,7 @@ struct StageParams {
     // applies P_q a^-1 V_q on every PML element
     int waa_skip;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
+    int order_rev;        // 1: workgroups take their tiles / blocks in reversed order (schedule-permutation check)
     double rk_a, rk_b, dt, src_g, alpha;
 };
 

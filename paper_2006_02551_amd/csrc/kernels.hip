@@ -65,7 +65,8 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
 
     const int u = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / B);
     const int lane = static_cast<int>(threadIdx.x) % B;
-    const int blk = __builtin_amdgcn_readfirstlane(remap_block(blockIdx.x, p.nblk_pml, p.nblk));
+    const int bid = p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
+    const int blk = __builtin_amdgcn_readfirstlane(remap_block(bid, p.nblk_pml, p.nblk));
     const bool pml = blk < p.nblk_pml;
     const int Nq = p.Nq;
 
@@ -302,7 +303,8 @@ __global__ __launch_bounds__(kApplyWaves * 64) void direct_apply_kernel(StagePar
     constexpr size_t MS = static_cast<size_t>(Np) * Np * B;  // one stored matrix
     __shared__ real xs[6][Np][B];  // E_u, H_u, PE_u, PH_u, w_E, w_H
 
-    const int blk = blockIdx.x / 3, ax = blockIdx.x % 3;
+    const int bid = p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
+    const int blk = bid / 3, ax = bid % 3;
     const int tid = static_cast<int>(threadIdx.x);
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     const real* __restrict__ qin = static_cast<const real*>(p.q_in);

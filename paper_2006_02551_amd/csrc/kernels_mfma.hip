@@ -3,9 +3,18 @@
 // Same mathematics and memory layout as the scalar-operand kernel in
 // kernels.hip (eqs. (26)-(29) with the upwind curl of eqs. (15)-(17), the
 // weight-adjusted inverse mass of eq. (21) and the LSERK4 update), but every
-// small dense product runs on V_MFMA_F64_16X16X4_F64 / V_MFMA_F32_16X16X4_F32:
+// small dense product runs on the matrix cores:
 //
 //   Out (M x 16 elements) = Op (M x K) * X (K x 16 elements)
+//
+// in steps of 16 output rows and 4 columns of K.  FP32 uses one
+// V_MFMA_F32_16X16X4_F32 per step.  FP64 uses up to four
+// V_MFMA_F64_4X4X4_4B_F64 per step, one per 4-row group v of the 16 rows (its
+// four blocks are the four 4-column groups of the 16 elements): on gfx950 that
+// instruction sustains about 1.5x the FP64 rate of V_MFMA_F64_16X16X4_F64
+// (76 against 49.5 TFLOP/s measured), its B operand and result lanes are those
+// of register v of the 16x16x4 product, and row groups past the operator's last
+// row are skipped instead of computed as padding.
 //
 // A tile is 16 elements (the columns), handled by six wavefronts, one per
 // field component u; a workgroup takes TPW adjacent tiles (1 or 2) so that its
@@ -46,19 +55,27 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Out += Op X for one 16-row step: AF is the lane's A operand (FP64: the four
+// words of the row groups v = 0..3), nv the number of leading row groups with
+// valid rows (FP64 skips the rest; FP32 computes all 16 rows).
 template <typename real>
 struct Mma;
 template <>
 struct Mma<double> {
     using v4 = v4d;
-    static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    using AF = v4d;
+    static __device__ __forceinline__ v4 run(AF a, double b, v4 c, int nv = 4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (v < nv) c[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[v], b, c[v], 0, 0, 0);
+        return c;
     }
 };
 template <>
 struct Mma<float> {
     using v4 = v4f;
-    static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+    using AF = float;
+    static __device__ __forceinline__ v4 run(AF a, float b, v4 c, int = 4) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
@@ -130,10 +147,12 @@ struct Shape {
     static constexpr int QMAX = 16 * QT;           // cubature points the sigma staging can hold
     static constexpr int RB = static_cast<int>(sizeof(real));
     // fragment words of each operator (V_q full tiles; P_q, D_r,s,t, LIFT compact last tile)
-    static constexpr int W_VQ = frag_words(QMAX, QT, SP, false);
-    static constexpr int W_PQ = frag_words(Np, PT, SQM, true);
-    static constexpr int W_D = frag_words(Np, PT, SP, true);
-    static constexpr int W_L = frag_words(Np, PT, SF, true);
+    static constexpr bool F64 = RB == 8;
+    static constexpr int NVL = (MR + 3) / 4;       // FP64: row groups of the last node tile
+    static constexpr int W_VQ = frag_words(QMAX, QT, SP, false, F64);
+    static constexpr int W_PQ = frag_words(Np, PT, SQM, true, F64);
+    static constexpr int W_D = frag_words(Np, PT, SP, true, F64);
+    static constexpr int W_L = frag_words(Np, PT, SF, true, F64);
     static constexpr int OFF_VQ = 0, OFF_PQ = W_VQ, OFF_D = OFF_PQ + W_PQ, OFF_L = OFF_D + 3 * W_D;
     static constexpr int NW = OFF_L + W_L;
     // LDS: operator fragments (shared by the workgroup), then per tile its E,H
@@ -251,7 +270,8 @@ void stage_mfma_kernel(StageParams p) {
     real* fl = fls[h];
 
     const int tile = __builtin_amdgcn_readfirstlane(
-        TPW * remap_tile(blockIdx.x, 4 / TPW * p.nblk_pml, 4 / TPW * p.nblk) + h);
+        TPW * remap_tile(p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x),
+                         4 / TPW * p.nblk_pml, 4 / TPW * p.nblk) + h);
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
     const int Nq = NQ > 0 ? NQ : p.Nq;
@@ -380,13 +400,43 @@ void stage_mfma_kernel(StageParams p) {
         }
     }
 
-    // Fragment word of lane `lane` for operator tile t (of nt) and k-step s (of K k-steps).
-    const int lq = F64 ? (lane & 15) : 4 * (lane & 3) + ((lane & 15) >> 2);
-    const int lp = (lane >> 4) * MR + (lq < MR ? lq : MR - 1);  // lane's word in a compact tile
-    auto frag = [&](int off, int t, int s, int K) -> real {
-        return t < PT - 1 ? fr[off + (t * K + s) * 64 + lane] : fr[off + (PT - 1) * K * 64 + s * 4 * MR + lp];
+    // A operand of lane `lane` for operator tile t and k-step s (of K k-steps); the last node tile is stored
+    // compact.  FP64: the four words of the row groups (layout in device.hpp); FP32: one word.
+    using AF = typename M::AF;
+    constexpr int NVL = S::NVL;
+    const int lq = 4 * (lane & 3) + ((lane & 15) >> 2);
+    const int lp = (lane >> 4) * MR + (lq < MR ? lq : MR - 1);  // FP32: lane's word in a compact tile
+    const int l4 = (lane >> 4) * 16 + (lane & 3) * 4;             // FP64: lane's first word in a full tile
+    const int l4c = (lane >> 4) * 4 * NVL + (lane & 3) * NVL;     // FP64: ... in a compact tile
+    auto frag = [&](int off, int t, int s, int K) -> AF {
+        if constexpr (F64) {
+            if (t < PT - 1) {
+                const real* p = fr + off + (t * K + s) * 64 + l4;
+                return AF{p[0], p[1], p[2], p[3]};
+            }
+            const real* p = fr + off + (PT - 1) * K * 64 + s * 16 * NVL + l4c;
+            AF a{0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < NVL; ++v) a[v] = p[v];
+            return a;
+        } else {
+            return t < PT - 1 ? fr[off + (t * K + s) * 64 + lane] : fr[off + (PT - 1) * K * 64 + s * 4 * MR + lp];
+        }
     };
-    auto fragq = [&](int t, int s) -> real { return fr[OFF_VQ + (t * SP + s) * 64 + lane]; };
+    auto fragq = [&](int t, int s) -> AF {
+        if constexpr (F64) {
+            const real* p = fr + OFF_VQ + (t * SP + s) * 64 + l4;
+            return AF{p[0], p[1], p[2], p[3]};
+        } else {
+            return fr[OFF_VQ + (t * SP + s) * 64 + lane];
+        }
+    };
+    // row groups with valid rows in node tile t and cubature tile t (FP64 skips the others)
+    auto nvn = [&](int t) -> int { return t < PT - 1 ? 4 : NVL; };
+    auto nvq = [&](int t) -> int {
+        const int rows = (NQ > 0 ? NQ : QMAX) - 16 * t;
+        return rows >= 16 ? 4 : (rows + 3) / 4;
+    };
     auto ehv = [&](int c, int node) -> real { return eh[(c * Np + node) * T + j]; };
 
     v4 R[PT];
@@ -440,7 +490,7 @@ void stage_mfma_kernel(StageParams p) {
             for (int s = r * S0; s < (r == 0 ? S0 : SF); ++s) {
                 const real b = fl[(u * NFH + 4 * (s - r * S0) + g) * T + j];
 #pragma unroll
-                for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L, t, s, SF), b, R[t]);
+                for (int t = 0; t < PT; ++t) R[t] = M::run(frag(OFF_L, t, s, SF), b, R[t], nvn(t));
             }
         }
     };
@@ -493,9 +543,9 @@ void stage_mfma_kernel(StageParams p) {
             const real gr = rb * xc - rc * xb, gs = sb * xc - sc * xb, gt = tb * xc - tc * xb;
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
-                R[t] = M::run(frag(OFF_D + 0 * W_D, t, s, SP), gr, R[t]);
-                R[t] = M::run(frag(OFF_D + 1 * W_D, t, s, SP), gs, R[t]);
-                R[t] = M::run(frag(OFF_D + 2 * W_D, t, s, SP), gt, R[t]);
+                R[t] = M::run(frag(OFF_D + 0 * W_D, t, s, SP), gr, R[t], nvn(t));
+                R[t] = M::run(frag(OFF_D + 1 * W_D, t, s, SP), gs, R[t], nvn(t));
+                R[t] = M::run(frag(OFF_D + 2 * W_D, t, s, SP), gt, R[t], nvn(t));
             }
         }
     }
@@ -550,12 +600,12 @@ void stage_mfma_kernel(StageParams p) {
             for (int s = 0; s < SP; ++s) {
                 const int node = 4 * s + g;
                 const bool ok = (SP * 4 == Np) || node < Np;
-                const real a = fragq(tq, s);
-                VF = M::run(a, ok ? ehv(u, node) : real(0), VF);
-                VP = M::run(a, ok ? bp[s] : real(0), VP);
+                const AF a = fragq(tq, s);
+                VF = M::run(a, ok ? ehv(u, node) : real(0), VF, nvq(tq));
+                VP = M::run(a, ok ? bp[s] : real(0), VP, nvq(tq));
                 if constexpr (ADJ) {
-                    VFf = M::run(a, ok ? ff[s] : real(0), VFf);
-                    VPf = M::run(a, ok ? fp[s] : real(0), VPf);
+                    VFf = M::run(a, ok ? ff[s] : real(0), VFf, nvq(tq));
+                    VPf = M::run(a, ok ? fp[s] : real(0), VPf, nvq(tq));
                 }
             }
 #pragma unroll
@@ -604,9 +654,9 @@ void stage_mfma_kernel(StageParams p) {
                 if (sq < SQ) {
 #pragma unroll
                     for (int t = 0; t < PT; ++t) {
-                        const real a = frag(OFF_PQ, t, sq, SQM);
-                        RP[t] = M::run(a, VP[v], RP[t]);
-                        R[t] = M::run(a, VF[v], R[t]);
+                        const AF a = frag(OFF_PQ, t, sq, SQM);
+                        RP[t] = M::run(a, VP[v], RP[t], nvn(t));
+                        R[t] = M::run(a, VF[v], R[t], nvn(t));
                     }
                 }
             }
@@ -704,7 +754,7 @@ void stage_mfma_kernel(StageParams p) {
                 const int sp = 4 * tp + v;
                 if (sp < SP) {
 #pragma unroll
-                    for (int t = 0; t < QT; ++t) Z[t] = M::run(fragq(t, sp), R[tp][v], Z[t]);
+                    for (int t = 0; t < QT; ++t) Z[t] = M::run(fragq(t, sp), R[tp][v], Z[t], nvq(t));
                 }
             }
         if (KAPPA) {
@@ -730,7 +780,7 @@ void stage_mfma_kernel(StageParams p) {
                 const int sq = 4 * tq + v;
                 if (sq < SQ) {
 #pragma unroll
-                    for (int t = 0; t < PT; ++t) O[t] = M::run(frag(OFF_PQ, t, sq, SQM), Z[tq][v], O[t]);
+                    for (int t = 0; t < PT; ++t) O[t] = M::run(frag(OFF_PQ, t, sq, SQM), Z[tq][v], O[t], nvn(t));
                 }
             }
 #pragma unroll

@@ -25,7 +25,8 @@ except ImportError:  # host-only use without torch
     torch = None
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwdg.so")
+# WDG_LIBRARY selects another build of the same library (the host-sanitizer build of build.py --sanitize)
+LIB_PATH = os.environ.get("WDG_LIBRARY") or os.path.join(HERE, "libwdg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2006_02551_amd.build`")
@@ -112,6 +113,8 @@ wdg_element_info = _sig("wdg_element_info", C.c_int32, _ctx, _dp, _dp, _dp, _ip,
 wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem_t))
 wdg_set_tiles = _sig("wdg_set_tiles", C.c_int32, _ctx, C.c_int32)
 wdg_set_waa_shortcut = _sig("wdg_set_waa_shortcut", C.c_int32, _ctx, C.c_int32)
+wdg_set_schedule = _sig("wdg_set_schedule", C.c_int32, _ctx, C.c_int32)
+wdg_autotune_cached = _sig("wdg_autotune_cached", C.c_int32, _ctx, C.c_int32, C.c_void_p, C.POINTER(C.c_int32))
 wdg_measure_mfma_peak = _sig("wdg_measure_mfma_peak", C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp)
 wdg_autotune = _sig("wdg_autotune", C.c_int32, _ctx, C.c_int32, _dp, C.c_void_p)
 wdg_step_graph = _sig("wdg_step_graph", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
@@ -357,9 +360,20 @@ class Simulation(Context):
         _check(wdg_set_tiles(self.h, int(tiles)), self.h)
         self.dims = self.get_dims()
 
+    def set_schedule(self, reversed_order):
+        _check(wdg_set_schedule(self.h, int(bool(reversed_order))), self.h)
+
     def set_waa_shortcut(self, on):
         """Skip (True) or apply (False, the default) the weight-adjusted inverse where it is the identity."""
         _check(wdg_set_waa_shortcut(self.h, int(bool(on))), self.h)
+
+    def autotune_cached(self, reps=5, stream=None):
+        """Applies the cached stage-kernel choice for this kind of context, or times and caches one;
+        returns True when the choice came from the cache."""
+        hit = C.c_int32(0)
+        _check(wdg_autotune_cached(self.h, int(reps), self._stream(stream), C.byref(hit)), self.h)
+        self.dims = self.get_dims()
+        return bool(hit.value)
 
     def autotune(self, reps=5, stream=None):
         """Times the stage kernels and keeps the fastest; returns us per launch

@@ -115,6 +115,24 @@ def test_loss_and_gradient_fp32_against_fp64_oracle(wdg, name, over, nsteps):
     assert err_j <= 1e-5 and err_g <= 2e-4
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_schedule_permutation(wdg, precision):
+    # reversed tile order: the loss and the final state bitwise equal; the sigma gradient (LDS atomic sums
+    # in no fixed order) to rounding
+    cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
+    _say(f"adjoint schedule permutation, precision {precision}")
+    res = []
+    for rev in (0, 1):
+        sim, osim, q0 = _pair(wdg, cfg, precision)
+        sim.set_schedule(rev)
+        J, g, gp = sim.loss_gradient(osim.dt, 10, SHELL_C1)
+        res.append((J, g, sim.get_fields()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][2], res[1][2])
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert np.max(np.abs(res[0][1] - res[1][1])) <= tol * np.max(np.abs(res[0][1]))
+
+
 def test_checkpoint_interval_and_empty_shell(wdg):
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
     _say("checkpoint intervals")

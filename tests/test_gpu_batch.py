@@ -84,6 +84,41 @@ def test_batch_members_match_oracle(wdg, precision, tol):
             assert err <= tol
 
 
+def test_autotune_cache_and_environment_overrides(wdg, tmp_path, monkeypatch):
+    cfg = inputs.config("c2", **{"mesh.n": 5})
+    _say("autotune cache and WDG_* overrides")
+    vx, ev = inputs.mesh_for(cfg)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("WDG_AUTOTUNE_CACHE", str(cache))
+
+    def make():
+        sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], wdg.WDG_FP32)
+        sim.set_fields(np.zeros((sim.dims.K, 12, sim.dims.Np)))
+        return sim
+    a = make()
+    first = a.autotune_cached(reps=3)
+    b = make()
+    assert b.autotune_cached(reps=3)  # same architecture, order, rule, precision, scheme and size class
+    assert (b.dims.kernel, b.dims.tiles) == (a.dims.kernel, a.dims.tiles)
+    if not first:
+        lines = cache.read_text().split("\n")
+        assert any(line.startswith("gfx") and "/N3/q24/f32/" in line for line in lines), lines
+    monkeypatch.setenv("WDG_KERNEL", "scalar")
+    assert make().dims.kernel == wdg.WDG_KERNEL_SCALAR
+    monkeypatch.setenv("WDG_KERNEL", "mfma")
+    monkeypatch.setenv("WDG_TILES", "1")
+    s = make()
+    assert s.dims.kernel == wdg.WDG_KERNEL_MFMA and s.dims.tiles == 1
+    monkeypatch.setenv("WDG_TILES", "3")
+    with pytest.raises(wdg.WdgError):
+        make()
+    monkeypatch.delenv("WDG_TILES")
+    monkeypatch.setenv("WDG_KERNEL", "fastest")
+    with pytest.raises(wdg.WdgError):
+        make()
+
+
 def test_graph_replay_matches_eager(wdg):
     import torch
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1})
