@@ -406,6 +406,26 @@ int32_t wdg_loss_gradient(wdg_ctx* ctx, double dt, int32_t nsteps, const wdg_she
                           int32_t checkpoint_interval, double* loss, double* grad_sigma,
                           double* grad_profile, void* hip_stream);
 
+/* ---- Allocation-free readout ---------------------------------------------- */
+
+/* Largest mesh (in blocks of 64 element slots, per class) of wdg_energy_noalloc:
+ * 32,768 blocks, a 256 KiB device array held by each GPU the library runs on. */
+#define WDG_NOALLOC_MAX_BLOCKS 32768
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * of wdg_energy, 1/2 sum_k J_k (E^T M E + H^T M H) of the current fields in
+ * FP64, written to out_device (a device pointer to one double) on hip_stream,
+ * without synchronising and without any allocation: the per-block partial sums
+ * go to a fixed device array (WDG_NOALLOC_MAX_BLOCKS doubles) instead of the
+ * context's scratch buffer.  The result is bitwise equal to wdg_energy's.
+ * Calls on one GPU share that array: calls that overlap in time on one GPU
+ * (two streams, two threads) race and must be ordered by the caller.  No
+ * finiteness check (the value stays on the device).  WDG_EINVAL for a null
+ * argument or a mesh of more than WDG_NOALLOC_MAX_BLOCKS blocks, WDG_ESTATE
+ * for a host-only context or unbound state, WDG_EHIP on a launch error. */
+int32_t wdg_energy_noalloc(wdg_ctx* ctx, double* out_device, void* hip_stream);
+
 /* ---- Measurement helper --------------------------------------------------- */
 
 /* Sustained rate of the matrix-core instruction the stage kernel uses for its

@@ -345,6 +345,7 @@ int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* m, wdg_ctx** out) {
         ctx->state_elems = (static_cast<int64_t>(ctx->S.nblk) + ctx->S.nblk_pml) * eh_words(ctx->S);
         if (!ctx->host_only) {
             hip_check(hipGetDevice(&ctx->device), "hipGetDevice");
+            hip_check(static_cast<hipError_t>(noalloc_setup(ctx->device)), "scratch symbol address");
             upload_setup(ctx.get());
         }
         return WDG_OK;

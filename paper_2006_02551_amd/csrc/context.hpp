@@ -158,4 +158,8 @@ int check_state(wdg_ctx* c);
 // Uploads sigma (and kappa) at the cubature points of the PML blocks from S.
 void upload_coefficients(wdg_ctx* c);
 
+// Device address of the allocation-free readout's scratch array on `device` (the current device),
+// looked up once per device; returns a hipError_t (0 on success).
+int noalloc_setup(int device);
+
 }  // namespace wdg

@@ -115,6 +115,7 @@ wdg_set_tiles = _sig("wdg_set_tiles", C.c_int32, _ctx, C.c_int32)
 wdg_set_waa_shortcut = _sig("wdg_set_waa_shortcut", C.c_int32, _ctx, C.c_int32)
 wdg_set_schedule = _sig("wdg_set_schedule", C.c_int32, _ctx, C.c_int32)
 wdg_autotune_cached = _sig("wdg_autotune_cached", C.c_int32, _ctx, C.c_int32, C.c_void_p, C.POINTER(C.c_int32))
+wdg_energy_noalloc = _sig("wdg_energy_noalloc", C.c_int32, _ctx, C.c_void_p, C.c_void_p)
 wdg_measure_mfma_peak = _sig("wdg_measure_mfma_peak", C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp)
 wdg_autotune = _sig("wdg_autotune", C.c_int32, _ctx, C.c_int32, _dp, C.c_void_p)
 wdg_step_graph = _sig("wdg_step_graph", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
