@@ -125,12 +125,16 @@ def measured_peaks():
         dst.copy_(src)
     b.record()
     torch.cuda.synchronize()
-    copy_gbs = 2 * 4 * n * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    torch_gbs = 2 * 4 * n * reps / (a.elapsed_time(b) * 1e-3) / 1e9
     del src, dst
-    return {"copy_gbs": copy_gbs, "mfma_f64_tflops": wdg.measure_mfma_peak(wdg.WDG_FP64, 4000),
+    lib_gbs = wdg.measure_copy_bandwidth(1 << 30)
+    return {"copy_gbs": max(torch_gbs, lib_gbs), "copy_torch_gbs": torch_gbs, "copy_library_gbs": lib_gbs,
+            "mfma_f64_tflops": wdg.measure_mfma_peak(wdg.WDG_FP64, 4000),
             "mfma_f32_tflops": wdg.measure_mfma_peak(wdg.WDG_FP32, 4000),
-            "how": "1 GiB FP32 tensor copy, 10 reps (2 GiB moved each); MFMA 16x16x4 chains, 8 per wavefront, "
-                   "32 wavefronts per compute unit"}
+            "how": "copy: the faster of a 1 GiB FP32 torch tensor copy (10 reps) and the library's 16-byte "
+                   "copy kernel over 1 GiB (best of 5), bytes read + written; MFMA: chains of 16x16x4 steps "
+                   "(FP64 as four 4x4x4 four-block instructions, as the stage kernel issues them), 8 per "
+                   "wavefront, 32 wavefronts per compute unit"}
 
 
 def measured_traffic(kernel):
@@ -225,7 +229,7 @@ def run_adjoint(precision):
             "dJ_dsigma_max": list(gp[:3]), "dJ_dL": list(gp[3:6]), "dJ_dorder": gp[6]}
 
 
-def run_batch(steps, warmup, seq_steps=50):
+def run_batch(steps, warmup, seq_steps=50, group_mb=128.0):
     """The batching form: 32 independent simulations (8^3 x 6 .. 24^3 x 6 tets, 1,282,008 in all, N=3, each
     with its own sigma profile and time step) stepped in one context in FP32 with captured two-step graphs,
     against the same simulations stepped one after another, each in a context of its own."""
@@ -254,6 +258,23 @@ def run_batch(steps, warmup, seq_steps=50):
     assert all(bool(abs(x) < 1e30) for x in (q.max(), q.min()))
     dofs = d.K * d.Np
     del b.sim
+    # the same batch with cache-sized step groups (aligned components, both steps of a captured pair group
+    # after group)
+    gb = Batch(cfg, wdg.WDG_FP32, group_mb=group_mb)
+    gb.sim.set_kernel(wdg.WDG_KERNEL_MFMA if chosen["kernel"] == "mfma" else wdg.WDG_KERNEL_SCALAR)
+    if chosen["kernel"] == "mfma":
+        gb.sim.set_tiles(chosen["tiles"])
+    gb.set_fields(gb.initial_fields())
+    gb.step(warmup, graph=True)
+    torch.cuda.synchronize()
+    ev[0].record(gb.stream)
+    gb.step(steps, graph=True)
+    ev[1].record(gb.stream)
+    torch.cuda.synchronize()
+    ms_grouped = ev[0].elapsed_time(ev[1])
+    ngroups = int(gb.step_groups.max()) + 1
+    dofs_g = gb.sim.dims.K * gb.sim.dims.Np
+    del gb.sim
     # the same simulations one after another
     ms_seq = 0.0
     stream = torch.cuda.current_stream()
@@ -268,10 +289,16 @@ def run_batch(steps, warmup, seq_steps=50):
         torch.cuda.synchronize()
         ms_seq += ev[0].elapsed_time(ev[3]) / seq_steps
         del sim
-    return {"value": dofs * steps / (ms_graph / 1e3), "ms_per_step": ms_graph / steps, "dtype": "f32",
+    best_ms = min(ms_graph, ms_grouped)
+    return {"value": dofs * steps / (best_ms / 1e3), "ms_per_step": best_ms / steps, "dtype": "f32",
+            "form": "grouped" if ms_grouped < ms_graph else "ungrouped",
+            "ungrouped_value": dofs * steps / (ms_graph / 1e3), "ungrouped_ms_per_step": ms_graph / steps,
+            "grouped_value": dofs_g * steps / (ms_grouped / 1e3), "grouped_ms_per_step": ms_grouped / steps,
+            "grouped_groups": ngroups, "group_mb": group_mb,
             "eager_value": dofs * steps / (ms_eager / 1e3),
             "sequential_value": dofs / (ms_seq / 1e3), "sequential_ms_per_step": ms_seq,
-            "speedup_vs_sequential": ms_seq / (ms_graph / steps),
+            "speedup_vs_sequential": ms_seq / (best_ms / steps),
+            "ungrouped_speedup_vs_sequential": ms_seq / (ms_graph / steps),
             "autotune_us_per_stage": tune, "chosen": chosen, "K": d.K, "K_pml": d.K_pml, "nsim": len(b.meshes),
             "steps": steps,
             "workload": "c4: 32 simulations, meshes 8^3x6 .. 24^3x6 perturbed tets (1,282,008 in all), N=3, "
@@ -452,6 +479,8 @@ def main():
                     help="run the loss-gradient leg only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--precision-form-only", action="store_true",
                     help="run the 384,000-tet N=4 precision-form leg only and print its JSON (e.g. under a profiler)")
+    ap.add_argument("--pf-steps", type=int, default=100,
+                    help="timed steps of the precision-form leg (e.g. fewer under a counter profiler)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run the 32-simulation batching leg only and print its JSON (e.g. under a profiler)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -490,7 +519,7 @@ def main():
     print(f"bench: measured peaks: copy {peaks['copy_gbs']:.0f} GB/s, MFMA FP64 {peaks['mfma_f64_tflops']:.1f} "
           f"TFLOP/s, FP32 {peaks['mfma_f32_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
     if args.precision_form_only:
-        print(json.dumps({"precision_form": run_precision_form(peaks=peaks), "measured_peaks": peaks}))
+        print(json.dumps({"precision_form": run_precision_form(steps=args.pf_steps, peaks=peaks), "measured_peaks": peaks}))
         return
     cfg = inputs.config("c2")
     print(f"bench: c2 workload, {args.warmup} warmup + {args.steps} timed steps, FP64", file=sys.stderr, flush=True)
@@ -515,7 +544,7 @@ def main():
               f"Table I contrast next", file=sys.stderr, flush=True)
         table_i = run_table_i()
         print("bench: precision form (c3, 384,000 tets, N=4) FP64 and FP32", file=sys.stderr, flush=True)
-        c3 = run_precision_form(peaks=peaks)
+        c3 = run_precision_form(steps=args.pf_steps, peaks=peaks)
         print(f"bench: c3 FP64 {c3['fp64']['value']:.3e} DOF/s, FP32 {c3['fp32']['value']:.3e} DOF/s, "
               f"FP32 vs FP64 {c3['fp32_rel_l2_vs_fp64']:.1e}", file=sys.stderr, flush=True)
     cpu = None

@@ -56,6 +56,10 @@ extern "C" {
 
 /* wdg_method.flags */
 #define WDG_HOST_ONLY 1 /* build the host-side setup only: no device memory, no stepping */
+/* start every face-connected component of the mesh (an independent simulation of a batch) at a block
+ * boundary of each element class, so that stages can be launched per group of components
+ * (wdg_set_step_groups); costs up to 63 padding slots per component and class */
+#define WDG_ALIGN_COMPONENTS 2
 
 typedef struct wdg_ctx wdg_ctx;
 
@@ -294,6 +298,20 @@ int32_t wdg_set_schedule(wdg_ctx* ctx, int32_t reversed);
  * max |P_q V_q - I| >= 1e-12 for the context's rule). */
 int32_t wdg_set_waa_shortcut(wdg_ctx* ctx, int32_t on);
 
+/* Groups of independent simulations for captured stepping (contexts created
+ * with WDG_ALIGN_COMPONENTS): group[k] (int32 [K], user element order) names
+ * the group 0..ngroups-1 of element k; every face-connected component must lie
+ * in one group, and each group must be a run of consecutive components
+ * (components are numbered by their lowest element index).  wdg_step_graph
+ * then captures, group after group, both steps of the pair for that group's
+ * element blocks only, so that a group's fields stay in the last-level cache
+ * over its ten stages; the arithmetic of every element is unchanged (results
+ * bitwise equal to ungrouped stepping).  ngroups = 0 or group = NULL removes
+ * the groups.  WDG_ESTATE for a context without aligned components, WDG_EINVAL
+ * for groups that split a component or are not runs of consecutive
+ * components. */
+int32_t wdg_set_step_groups(wdg_ctx* ctx, int32_t ngroups, const int32_t* group);
+
 /* Per-element factor on the time step, double [K] in user element order (NULL
  * removes it): element k advances with dt * scale[k], so independent
  * simulations held in one context (disjoint meshes) each keep their own stable
@@ -344,6 +362,10 @@ int32_t wdg_element_info(const wdg_ctx* ctx, double* J, double* Fscale, double* 
                          int32_t* etoe, int32_t* etof, int32_t* is_pml);
 
 int32_t wdg_memory_report(const wdg_ctx* ctx, wdg_mem_t* out);
+
+/* Device slot (block * 64 + lane of the blocked layout) of every element,
+ * int32 [K] in user element order. */
+int32_t wdg_element_slots(const wdg_ctx* ctx, int32_t* slot);
 
 /* ---- Conductivity at the cubature points and differentiation ------------- */
 
@@ -428,16 +450,25 @@ int32_t wdg_energy_noalloc(wdg_ctx* ctx, double* out_device, void* hip_stream);
 
 /* ---- Measurement helper --------------------------------------------------- */
 
-/* Sustained rate of the matrix-core instruction the stage kernel uses for its
- * small dense products (the 16x16x4 FP64 or FP32 MFMA shape), measured on the
- * current device: eight workgroups of four wavefronts per compute unit, each
- * wavefront running eight independent accumulator chains of `iters`
- * instructions; best of three timed launches after one untimed launch.  The roofline's measured compute peak; not part of
- * the method.  precision WDG_FP64 or WDG_FP32; *tflops receives TFLOP/s (one
- * multiply-add = 2 flops).  Allocates and frees a small device buffer;
- * synchronises hip_stream.  WDG_EINVAL for bad arguments, WDG_EHIP on a
- * launch error. */
+/* Sustained rate of the matrix-core instructions the stage kernel uses for its
+ * small dense products, measured on the current device: per 16x16x4 step one
+ * V_MFMA_F32_16X16X4_F32 (FP32) or four V_MFMA_F64_4X4X4_4B_F64 (FP64), eight
+ * workgroups of four wavefronts per compute unit, each wavefront running eight
+ * independent accumulator chains of `iters` steps; best of three timed
+ * launches after one untimed launch.  The roofline's measured compute peak;
+ * not part of the method.  precision WDG_FP64 or WDG_FP32; *tflops receives
+ * TFLOP/s (one multiply-add = 2 flops).  Allocates and frees a small device
+ * buffer; synchronises hip_stream.  WDG_EINVAL for bad arguments, WDG_EHIP on
+ * a launch error. */
 int32_t wdg_measure_mfma_peak(int32_t precision, int32_t iters, void* hip_stream, double* tflops);
+
+/* Device-memory bandwidth of a plain copy of `bytes` bytes (a multiple of 16,
+ * at least 1 MiB) between two buffers allocated and freed inside the call:
+ * 16-byte loads and stores, four per thread; best of five timed launches after
+ * one untimed launch.  *gbs receives (bytes read + bytes written) / time in
+ * GB/s.  Synchronises hip_stream.  WDG_EINVAL for bad arguments, WDG_ENOMEM,
+ * WDG_EHIP on a launch error. */
+int32_t wdg_measure_copy_bandwidth(int64_t bytes, void* hip_stream, double* gbs);
 
 #ifdef __cplusplus
 }

@@ -119,6 +119,10 @@ int adjoint_stage(wdg_ctx* c, const void* z, const void* y, const void* qhat_in,
     p.Jk = static_cast<const double*>(c->Jk.p);
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
+    p.pml0 = 0;
+    p.npml = S.nblk_pml;
+    p.int0 = S.nblk_pml;
+    p.nint = S.nblk - S.nblk_pml;
     p.Nq = S.ref.Nq;
     p.read_res = 1;
     p.order_rev = c->order_rev ? 1 : 0;

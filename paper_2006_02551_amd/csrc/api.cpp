@@ -265,6 +265,17 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     p.waa_skip = (c->waa_skip && c->waa_identity) ? 1 : 0;
     p.nblk_pml = S.nblk_pml;
     p.nblk = S.nblk;
+    if (c->range_on) {  // one group of independent simulations (captured grouped stepping)
+        p.pml0 = c->range[0];
+        p.npml = c->range[1];
+        p.int0 = c->range[2];
+        p.nint = c->range[3];
+    } else {
+        p.pml0 = 0;
+        p.npml = S.nblk_pml;
+        p.int0 = S.nblk_pml;
+        p.nint = S.nblk - S.nblk_pml;
+    }
     p.Nq = S.ref.Nq;
     p.read_res = read_res ? 1 : 0;
     p.order_rev = c->order_rev ? 1 : 0;
@@ -335,7 +346,7 @@ int32_t wdg_create(const wdg_mesh* mesh, const wdg_method* m, wdg_ctx** out) {
         pp.order = m->profile_order;
         pp.kappa_max = m->kappa_max;
         ctx->S = build_setup(mesh->nv, mesh->vxyz, mesh->K, mesh->etov, mesh->vertex_id, m->N, m->nq, m->cub_rst,
-                             m->cub_w, pp, m->flux_alpha);
+                             m->cub_w, pp, m->flux_alpha, (m->flags & WDG_ALIGN_COMPONENTS) != 0);
         // neighbour traces are addressed by 32-bit signed word offsets into the E,H part
         if (static_cast<int64_t>(ctx->S.nblk) * eh_words(ctx->S) > kMaxEhWords)
             throw Error(WDG_EINVAL, "mesh too large: the E,H part exceeds 2^31 - 1 words (32-bit neighbour offsets)");
@@ -624,6 +635,12 @@ int32_t wdg_energy(wdg_ctx* c, double* out, void* hip_stream) {
         if (!std::isfinite(*out)) return fail(c, WDG_ENONFINITE, "energy is not finite");
         return WDG_OK;
     });
+}
+
+int32_t wdg_element_slots(const wdg_ctx* c, int32_t* slot) {
+    if (!c || !slot) return WDG_EINVAL;
+    std::copy(c->S.perm.begin(), c->S.perm.end(), slot);
+    return WDG_OK;
 }
 
 int32_t wdg_node_coords(const wdg_ctx* c, double* xyz) {

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -127,6 +128,57 @@ int32_t wdg_set_tiles(wdg_ctx* c, int32_t tiles) {
     return WDG_OK;
 }
 
+int32_t wdg_set_step_groups(wdg_ctx* c, int32_t ngroups, const int32_t* group) {
+    if (!c || ngroups < 0) return WDG_EINVAL;
+    if (ngroups == 0 || !group) {
+        c->drop_graph();
+        c->groups.clear();
+        return WDG_OK;
+    }
+    const Setup& S = c->S;
+    if (!S.aligned) return fail(c, WDG_ESTATE, "step groups need a context created with WDG_ALIGN_COMPONENTS");
+    return guarded(c, [&]() -> int {
+        std::vector<int> cg(S.ncomp, -1);  // group of each component
+        for (int k = 0; k < S.K; ++k) {
+            const int g = group[k];
+            if (g < 0 || g >= ngroups) return fail(c, WDG_EINVAL, "group index out of range");
+            int& x = cg[S.comp[k]];
+            if (x >= 0 && x != g) return fail(c, WDG_EINVAL, "a face-connected component spans two groups");
+            x = g;
+        }
+        std::vector<std::array<int, 4>> out(ngroups, std::array<int, 4>{0, 0, 0, 0});
+        std::vector<int> first(ngroups, -1), last(ngroups, -1);
+        for (int cp = 0; cp < S.ncomp; ++cp) {
+            const int g = cg[cp];
+            if (first[g] < 0) first[g] = cp;
+            else if (last[g] != cp - 1) return fail(c, WDG_EINVAL, "a group is not a run of consecutive components");
+            last[g] = cp;
+        }
+        for (int g = 0; g < ngroups; ++g) {
+            if (first[g] < 0) return fail(c, WDG_EINVAL, "an empty group");
+            // blocks of the run in each class (components of a run are laid out one after another)
+            int p0 = 0, p1 = 0, i0 = 0, i1 = 0;
+            bool hp = false, hi = false;
+            for (int cp = first[g]; cp <= last[g]; ++cp) {
+                if (S.comp_pml1[cp] > S.comp_pml0[cp]) {
+                    p0 = hp ? std::min(p0, S.comp_pml0[cp]) : S.comp_pml0[cp];
+                    p1 = hp ? std::max(p1, S.comp_pml1[cp]) : S.comp_pml1[cp];
+                    hp = true;
+                }
+                if (S.comp_int1[cp] > S.comp_int0[cp]) {
+                    i0 = hi ? std::min(i0, S.comp_int0[cp]) : S.comp_int0[cp];
+                    i1 = hi ? std::max(i1, S.comp_int1[cp]) : S.comp_int1[cp];
+                    hi = true;
+                }
+            }
+            out[g] = {p0, p1 - p0, hi ? i0 : S.nblk_pml, i1 - i0};
+        }
+        c->drop_graph();
+        c->groups.swap(out);
+        return WDG_OK;
+    });
+}
+
 int32_t wdg_set_schedule(wdg_ctx* c, int32_t reversed) {
     if (!c || (reversed != 0 && reversed != 1)) return WDG_EINVAL;
     c->drop_graph();
@@ -217,7 +269,21 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
                 const int64_t s0 = c->steps;
                 hipGraph_t g = nullptr;
                 hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-                const int rc = launch_steps(c, dt, 2, s);
+                int rc = WDG_OK;
+                if (c->groups.empty()) {
+                    rc = launch_steps(c, dt, 2, s);
+                } else {
+                    // group after group, both steps on that group's blocks (its fields stay in the
+                    // last-level cache over the ten stages); each group starts from the same buffers
+                    for (size_t gi = 0; gi < c->groups.size() && rc == WDG_OK; ++gi) {
+                        c->cur = cur0;
+                        c->t = t0;
+                        c->range = c->groups[gi];
+                        c->range_on = true;
+                        rc = launch_steps(c, dt, 2, s);
+                        c->range_on = false;
+                    }
+                }
                 const hipError_t ec = hipStreamEndCapture(s, &g);
                 c->cur = cur0;
                 c->t = t0;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -83,6 +84,11 @@ struct wdg_ctx {
     bool waa_identity = false;  // kappa = 1 and P_q V_q = I to rounding
     bool waa_skip = false;      // skip the weight-adjusted inverse (only where waa_identity holds; opt-in)
     bool order_rev = false;     // workgroups take tiles in reversed order (schedule-permutation check)
+    // step groups (aligned layouts only): per group [pml0, npml, int0, nint] block ranges; stage launches
+    // cover range while range_on
+    std::vector<std::array<int, 4>> groups;
+    bool range_on = false;
+    std::array<int, 4> range{};
     int kernel = WDG_KERNEL_SCALAR;
     int tpw = 2;  // tiles per workgroup of the matrix-core kernel
     // PML scheme (WDG_PML_*) and its per-element data: the direct scheme's stored

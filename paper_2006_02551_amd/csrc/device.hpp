@@ -55,6 +55,21 @@ constexpr int frag_words(int rows, int tiles, int ksteps, bool compact, bool f64
     const int last = f64 ? 16 * ((m + 3) / 4) : 4 * m;
     return compact ? ((tiles - 1) * 64 + last) * ksteps : tiles * 64 * ksteps;
 }
+// Position `bid` of a launch over n0 + n1 work items (n0 of a first range starting at base0, n1 of a second
+// starting at base1), mapped so that each of the eight XCDs (consecutive workgroup IDs go to consecutive
+// XCDs) walks a contiguous run of items inside each range: neighbour traces then tend to hit its own L2.
+__device__ __forceinline__ int remap_range(int bid, int base0, int n0, int base1, int n1) {
+    int base = base0, n = n0, j = bid;
+    if (bid >= n0) {
+        base = base1;
+        n = n1;
+        j = bid - n0;
+    }
+    const int x = j & 7, i = j >> 3;
+    const int q = n >> 3, r = n & 7;
+    return base + x * q + (x < r ? x : r) + i;
+}
+
 // Number of 1 KiB chunks that hold nwords fragment words.
 constexpr int frag_chunks(int nwords, int word_bytes) { return (nwords * word_bytes + 1023) / 1024; }
 
@@ -97,6 +112,9 @@ struct StageParams {
     int waa_skip;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
     int order_rev;        // 1: workgroups take their tiles / blocks in reversed order (schedule-permutation check)
+    // blocks this launch covers: [pml0, pml0 + npml) of the PML class and [int0, int0 + nint) of the vacuum
+    // class (every block unless a launch is restricted to a group of independent simulations)
+    int pml0, npml, int0, nint;
     double rk_a, rk_b, dt, src_g, alpha;
 };
 

@@ -77,12 +77,21 @@ struct Setup {
     // device ordering
     std::vector<int> perm;               // user element -> slot (blk*B + lane)
     std::vector<int> slot_elem;          // slot -> user element or -1
+    // face-connected components (independent simulations of a batch), numbered by their lowest element
+    int ncomp = 0;
+    std::vector<int> comp;               // [K] component of each element
+    // with aligned components: blocks [blk0, blk1) of each component in the PML class and in the vacuum
+    // class (empty ranges otherwise)
+    bool aligned = false;
+    std::vector<int> comp_pml0, comp_pml1, comp_int0, comp_int1;
     double dt_unit = 0.0;
 };
 
 // vertex_id: null, or [nv] identification used by the face connectivity (periodic meshes).
+// align_components: every face-connected component starts at a block boundary in each class.
 Setup build_setup(int nv, const double* vxyz, int K, const int* etov, const int* vertex_id, int N, int nq,
-                  const double* rst, const double* w, const PmlParams& pml, double flux_alpha);
+                  const double* rst, const double* w, const PmlParams& pml, double flux_alpha,
+                  bool align_components = false);
 
 // Element containing a point (largest smallest barycentric coordinate, lowest
 // index on ties) and the Lagrange weights [Np] at it.

@@ -44,18 +44,7 @@ struct Ord {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup id mod 8).
 // Map them so that every XCD walks a contiguous, spatially coherent run of
-// blocks inside each class; neighbour traces then tend to hit its own L2.
-__device__ __forceinline__ int remap_block(int bid, int nblk_pml, int nblk) {
-    int base = 0, n = nblk_pml;
-    if (bid >= nblk_pml) {
-        base = nblk_pml;
-        n = nblk - nblk_pml;
-    }
-    const int j = bid - base;
-    const int x = j & 7, i = j >> 3;
-    const int q = n >> 3, r = n & 7;
-    return base + x * q + (x < r ? x : r) + i;
-}
+// blocks inside each class (remap_range); neighbour traces then tend to hit its own L2.
 
 template <typename real, int N, bool KAPPA, int MODE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
@@ -66,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(StageParams p) {
     const int u = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / B);
     const int lane = static_cast<int>(threadIdx.x) % B;
     const int bid = p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
-    const int blk = __builtin_amdgcn_readfirstlane(remap_block(bid, p.nblk_pml, p.nblk));
+    const int blk = __builtin_amdgcn_readfirstlane(remap_range(bid, p.pml0, p.npml, p.int0, p.nint));
     const bool pml = blk < p.nblk_pml;
     const int Nq = p.Nq;
 
@@ -304,7 +293,7 @@ __global__ __launch_bounds__(kApplyWaves * 64) void direct_apply_kernel(StagePar
     __shared__ real xs[6][Np][B];  // E_u, H_u, PE_u, PH_u, w_E, w_H
 
     const int bid = p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x);
-    const int blk = bid / 3, ax = bid % 3;
+    const int blk = p.pml0 + bid / 3, ax = bid % 3;
     const int tid = static_cast<int>(threadIdx.x);
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     const real* __restrict__ qin = static_cast<const real*>(p.q_in);
@@ -419,14 +408,16 @@ __global__ __launch_bounds__(256) void sum_kernel(const double* partial, int n, 
 
 template <typename real, int N, bool KAPPA, int MODE>
 int launch_stage_t(const StageParams& p, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<real, N, KAPPA, MODE>), dim3(p.nblk), dim3(kThreads), 0, s, p);
+    if (p.npml + p.nint == 0) return 0;
+    hipLaunchKernelGGL((stage_kernel<real, N, KAPPA, MODE>), dim3(p.npml + p.nint), dim3(kThreads), 0, s, p);
     return static_cast<int>(hipGetLastError());
 }
 
 template <typename real, int N>
 int launch_apply(const StageParams& p, hipStream_t s) {
     if (p.nblk_pml == 0) return 0;
-    hipLaunchKernelGGL((direct_apply_kernel<real, N>), dim3(3 * p.nblk_pml), dim3(kApplyWaves * 64), 0, s, p);
+    if (p.npml == 0) return 0;
+    hipLaunchKernelGGL((direct_apply_kernel<real, N>), dim3(3 * p.npml), dim3(kApplyWaves * 64), 0, s, p);
     return static_cast<int>(hipGetLastError());
 }
 

@@ -86,18 +86,8 @@ struct Ord {
     static constexpr int Nfp = (N + 1) * (N + 2) / 2;
 };
 
-// Tiles: every element block of 64 slots is four tiles of 16; PML tiles first.
-__device__ __forceinline__ int remap_tile(int bid, int ntile_pml, int ntile) {
-    int base = 0, n = ntile_pml;
-    if (bid >= ntile_pml) {
-        base = ntile_pml;
-        n = ntile - ntile_pml;
-    }
-    const int jj = bid - base;
-    const int x = jj & 7, i = jj >> 3;
-    const int q = n >> 3, r = n & 7;
-    return base + x * q + (x < r ? x : r) + i;
-}
+// Tiles: every element block of 64 slots is four tiles of 16; PML tiles first.  A workgroup takes TPW
+// adjacent tiles; its position in the launch maps to a tile group by remap_range.
 
 // Copies nseg row segments of `seg_bytes` (16 elements of one row) into LDS
 // with direct 16-byte global->LDS loads, 1 KiB per wavefront instruction.
@@ -270,8 +260,8 @@ void stage_mfma_kernel(StageParams p) {
     real* fl = fls[h];
 
     const int tile = __builtin_amdgcn_readfirstlane(
-        TPW * remap_tile(p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x),
-                         4 / TPW * p.nblk_pml, 4 / TPW * p.nblk) + h);
+        TPW * remap_range(p.order_rev ? static_cast<int>(gridDim.x - 1 - blockIdx.x) : static_cast<int>(blockIdx.x),
+                          4 / TPW * p.pml0, 4 / TPW * p.npml, 4 / TPW * p.int0, 4 / TPW * p.nint) + h);
     const int blk = tile >> 2, sub = tile & 3;
     const bool pml = blk < p.nblk_pml;
     const int Nq = NQ > 0 ? NQ : p.Nq;
@@ -376,29 +366,20 @@ void stage_mfma_kernel(StageParams p) {
                 if (((0 * PT + t) * 4 + v) / UPS == s)
                     rP[t][v] = GATHER_ALL ? ldg(rs + (pml ? pbase : ebase), lo)
                                           : ((!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0));
-                // (the FP32 adjoint reads its update base where it is used: fewer registers live at
-                // its two-workgroup occupancy)
+                // (the adjoint reads its update base where it is used: fewer registers live through the
+                // curl and the PML terms, no spills)
                 if (((1 * PT + t) * 4 + v) / UPS == s)
                     qP[t][v] = GATHER_ALL ? ldg(qb + (pml ? pbase : ebase), lo)
-                                          : (((!ADJ || F64) && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0));
+                                          : ((!ADJ && !DIRECT && pml) ? ldg(qb + pbase, lo) : real(0));
                 if (!(LATE_FLUX && !ADJ) && ((2 * PT + t) * 4 + v) / UPS == s)  // else issued before the late flux
-                    rE[t][v] = ADJ ? (F64 ? ldg(qb + ebase, lo) : real(0))
+                    rE[t][v] = ADJ ? real(0)
                                    : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, lo) : real(0));
             }
     };
-    // adjoint: this component's forward fields at the stage input, for the sigma gradient
+    // adjoint: this component's forward fields at the stage input, for the sigma gradient (loaded at the
+    // start of the PML terms, the only place they are used, so that they are not live through the curl)
     constexpr int SPA = ADJ ? SP : 1;
     real ff[SPA], fp[SPA];
-    if constexpr (ADJ) {
-        const real* __restrict__ qf = static_cast<const real*>(p.q_fwd);
-#pragma unroll
-        for (int s = 0; s < SP; ++s) {
-            const int node = 4 * s + g;
-            const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
-            ff[s] = pml ? ldg(qf + ebase, static_cast<unsigned>(j + nd * B)) : real(0);
-            fp[s] = pml ? ldg(qf + pbase, static_cast<unsigned>(j + nd * B)) : real(0);
-        }
-    }
 
     // A operand of lane `lane` for operator tile t and k-step s (of K k-steps); the last node tile is stored
     // compact.  FP64: the four words of the row groups (layout in device.hpp); FP32: one word.
@@ -565,7 +546,7 @@ void stage_mfma_kernel(StageParams p) {
                 if (node < Np) {
                     const unsigned lo = static_cast<unsigned>(j + node * B);
                     if constexpr (ADJ) {
-                        const real qn = (F64 ? qP[t][v] : ldg(qb + pbase, lo)) + dt * RP[t][v];
+                        const real qn = ldg(qb + pbase, lo) + dt * RP[t][v];
                         stg(qo + pbase, lo, qn);
                         if (yn) stg(yn + pbase, lo, yna * ldg(rs + pbase, lo) + ynb * qn);  // rs holds y here
                     } else {
@@ -590,6 +571,16 @@ void stage_mfma_kernel(StageParams p) {
         // dd/dsigma_u = 1) goes to the LDS accumulator, weighted by dt J w_q.  Last rhs_P += P_q t2 and
         // R -= P_q t1 over the tile's k-steps.
         const double wJ = ADJ ? p.dt * p.Jk[static_cast<size_t>(blk) * B + e] : 0.0;
+        if constexpr (ADJ) {
+            const real* __restrict__ qf = static_cast<const real*>(p.q_fwd);
+#pragma unroll
+            for (int s = 0; s < SP; ++s) {
+                const int node = 4 * s + g;
+                const int nd = ((SP * 4 == Np) || node < Np) ? node : 0;
+                ff[s] = ldg(qf + ebase, static_cast<unsigned>(j + nd * B));
+                fp[s] = ldg(qf + pbase, static_cast<unsigned>(j + nd * B));
+            }
+        }
         v4 RP[PT];
 #pragma unroll
         for (int t = 0; t < PT; ++t) RP[t] = v4{0, 0, 0, 0};
@@ -797,7 +788,7 @@ void stage_mfma_kernel(StageParams p) {
                 const unsigned lo = static_cast<unsigned>(j + node * B);
                 if constexpr (ADJ) {
                     // L* y = -L_vac(-alpha) z + P_q(-b VZ + kappa^-1 VY) = -R
-                    const real qn = (F64 ? rE[t][v] : ldg(qb + ebase, lo)) - dt * R[t][v];
+                    const real qn = ldg(qb + ebase, lo) - dt * R[t][v];
                     stg(qo + ebase, lo, qn);
                     if (yn) stg(yn + ebase, lo, yna * ehv(u, node) + ynb * qn);
                 } else {
@@ -831,7 +822,8 @@ int launch_t(const StageParams& p, hipStream_t s) {
     if constexpr (Shape<real, N, QT, ADJ, TPW>::LDS > 160 * 1024) {
         return static_cast<int>(hipErrorInvalidConfiguration);  // more LDS than a compute unit has
     } else {
-        const dim3 grid(4 / TPW * p.nblk), block(TPW * kMfmaThreads);
+        if (p.npml + p.nint == 0) return 0;
+        const dim3 grid(4 / TPW * (p.npml + p.nint)), block(TPW * kMfmaThreads);
         constexpr int RQ = rule_nq<N>();
         if constexpr (MODE == kPmlWaa && !K && (RQ + 15) / 16 == QT) {
             if (p.Nq == RQ) {

@@ -121,7 +121,7 @@ double profile_ratio(double x, double lo, double hi, double L, double p) {
 }
 
 Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const int* vertex_id, int N, int nq,
-                  const double* rst, const double* w, const PmlParams& pml, double flux_alpha) {
+                  const double* rst, const double* w, const PmlParams& pml, double flux_alpha, bool align_components) {
     if (K <= 0 || nv <= 0 || !vxyz || !etov_in) throw Error(-2, "empty mesh");
     if (vertex_id)
         for (int i = 0; i < nv; ++i)
@@ -382,33 +382,66 @@ Setup build_setup(int nv, const double* vxyz, int K, const int* etov_in, const i
     for (const auto& x : int_list) int_order.push_back(x.second);
     // Runs are grown within consecutive chunks of 1024 elements of the Morton order: the chunks keep
     // the curve's large-scale locality (what the L2 caches see across concurrent workgroups; runs
-    // grown over the whole class wander and raised the stage kernel's HBM reads by a fifth).
+    // grown over the whole class wander and raised the stage kernel's HBM reads by a fifth).  With
+    // aligned components the chunks restart at every component.
     constexpr size_t kChunk = 1024;
+    S.ncomp = 1 + *std::max_element(comp.begin(), comp.end());
+    S.comp = comp;
+    S.aligned = align_components;
     for (auto* ord : {&pml_order, &int_order}) {
         std::vector<int> out;
         out.reserve(ord->size());
-        for (size_t i = 0; i < ord->size(); i += kChunk) {
-            const std::vector<int> part(ord->begin() + i, ord->begin() + std::min(ord->size(), i + kChunk));
+        size_t i = 0;
+        while (i < ord->size()) {
+            size_t end = std::min(ord->size(), i + kChunk);
+            if (align_components)
+                for (size_t e = i + 1; e < end; ++e)
+                    if (comp[(*ord)[e]] != comp[(*ord)[i]]) {
+                        end = e;
+                        break;
+                    }
+            const std::vector<int> part(ord->begin() + i, ord->begin() + end);
             const std::vector<int> grown = grow_runs(part, S.etoe, K, 16);
             out.insert(out.end(), grown.begin(), grown.end());
+            i = end;
         }
         *ord = out;
     }
     S.K_pml = static_cast<int>(pml_list.size());
     const int B = S.B;
-    S.nblk_pml = (S.K_pml + B - 1) / B;
-    const int nblk_int = (static_cast<int>(int_list.size()) + B - 1) / B;
-    S.nblk = S.nblk_pml + nblk_int;
+    // slots of one class: consecutive, or with every component starting at a block boundary
+    auto place = [&](const std::vector<int>& ord, int first_blk, std::vector<int>& c0, std::vector<int>& c1) {
+        std::vector<int> slots(ord.size());
+        int slot = first_blk * B;
+        for (size_t i = 0; i < ord.size(); ++i) {
+            if (align_components && i > 0 && comp[ord[i]] != comp[ord[i - 1]]) slot = (slot + B - 1) / B * B;
+            slots[i] = slot++;
+        }
+        const int nblk_class = (slot - first_blk * B + B - 1) / B;
+        if (align_components) {
+            c0.assign(S.ncomp, 0);
+            c1.assign(S.ncomp, 0);
+            for (size_t i = 0; i < ord.size(); ++i) {
+                const int c = comp[ord[i]], b = slots[i] / B;
+                if (i == 0 || comp[ord[i - 1]] != c) c0[c] = b;
+                c1[c] = b + 1;
+            }
+        }
+        return std::make_pair(slots, nblk_class);
+    };
+    const auto pp = place(pml_order, 0, S.comp_pml0, S.comp_pml1);
+    S.nblk_pml = pp.second;
+    const auto ip = place(int_order, S.nblk_pml, S.comp_int0, S.comp_int1);
+    S.nblk = S.nblk_pml + ip.second;
     S.perm.assign(K, -1);
     S.slot_elem.assign(static_cast<size_t>(S.nblk) * B, -1);
     for (size_t i = 0; i < pml_order.size(); ++i) {
-        S.perm[pml_order[i]] = static_cast<int>(i);
-        S.slot_elem[i] = pml_order[i];
+        S.perm[pml_order[i]] = pp.first[i];
+        S.slot_elem[pp.first[i]] = pml_order[i];
     }
     for (size_t i = 0; i < int_order.size(); ++i) {
-        const int slot = S.nblk_pml * B + static_cast<int>(i);
-        S.perm[int_order[i]] = slot;
-        S.slot_elem[slot] = int_order[i];
+        S.perm[int_order[i]] = ip.first[i];
+        S.slot_elem[ip.first[i]] = int_order[i];
     }
     return S;
 }

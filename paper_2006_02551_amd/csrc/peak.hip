@@ -1,9 +1,10 @@
-// Measurement helper: sustained matrix-core rate of the 16x16x4 MFMA shapes the stage kernel uses
-// (V_MFMA_F64_16X16X4_F64, V_MFMA_F32_16X16X4_F32), for the roofline's measured compute peak.
+// Measurement helpers for the roofline's measured peaks: the sustained rate of the matrix-core
+// instruction the stage kernel uses (FP64: V_MFMA_F64_4X4X4_4B_F64, FP32: V_MFMA_F32_16X16X4_F32), and the
+// device-memory bandwidth of a plain copy.
 //
-// Every wavefront runs CH independent accumulator chains of `iters` MFMAs each, so the matrix pipe of a
-// SIMD always has independent work; the grid puts several workgroups on every compute unit.  The
-// accumulators are written out at the end so that nothing is dead code.
+// Every wavefront runs independent accumulator chains of `iters` MFMAs each, so the matrix pipe of a SIMD
+// always has independent work; the grid puts several workgroups on every compute unit.  The accumulators
+// are written out at the end so that nothing is dead code.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -21,9 +22,13 @@ constexpr int kThreads = 256;  // four wavefronts per workgroup
 template <typename real>
 struct PeakMma;
 template <>
-struct PeakMma<double> {
+struct PeakMma<double> {  // four four-block 4x4x4 products = one 16x16x4 step, as the stage kernel issues them
     using v4 = v4d;
-    static __device__ __forceinline__ v4 run(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c[v] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c[v], 0, 0, 0);
+        return c;
+    }
 };
 template <>
 struct PeakMma<float> {
@@ -86,8 +91,66 @@ extern "C" int32_t wdg_measure_mfma_peak(int32_t precision, int32_t iters, void*
     (void)hipEventDestroy(e1);
     (void)hipFree(out);
     if (rc != WDG_OK) return rc;
-    // one 16x16x4 MFMA per wavefront is 16 * 16 * 4 multiply-adds
+    // one 16x16x4 step per wavefront is 16 * 16 * 4 multiply-adds
     const double flops = 2.0 * 16 * 16 * 4 * static_cast<double>(kChains) * iters * (static_cast<double>(blocks) * kThreads / 64);
     *tflops = flops / (static_cast<double>(best) * 1e-3) / 1e12;
+    return WDG_OK;
+}
+
+namespace {
+
+constexpr int kCopyUnroll = 4;
+
+__global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+    const size_t base = static_cast<size_t>(blockIdx.x) * (256 * kCopyUnroll) + threadIdx.x;
+    uint4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + static_cast<size_t>(u) * 256;
+        if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const size_t i = base + static_cast<size_t>(u) * 256;
+        if (i < n) dst[i] = v[u];
+    }
+}
+
+}  // namespace
+
+extern "C" int32_t wdg_measure_copy_bandwidth(int64_t bytes, void* hip_stream, double* gbs) {
+    if (!gbs || bytes < (1 << 20) || bytes % 16 != 0) return WDG_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void *src = nullptr, *dst = nullptr;
+    if (hipMalloc(&src, static_cast<size_t>(bytes)) != hipSuccess) return WDG_ENOMEM;
+    if (hipMalloc(&dst, static_cast<size_t>(bytes)) != hipSuccess) {
+        (void)hipFree(src);
+        return WDG_ENOMEM;
+    }
+    int32_t rc = hipMemsetAsync(src, 0, static_cast<size_t>(bytes), s) == hipSuccess ? WDG_OK : WDG_EHIP;
+    const size_t n = static_cast<size_t>(bytes) / 16;
+    const unsigned blocks = static_cast<unsigned>((n + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll));
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 0.0f;
+    for (int rep = 0; rep < 6 && rc == WDG_OK; ++rep) {  // the first launch is untimed
+        (void)hipEventRecord(e0, s);
+        hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+        (void)hipEventRecord(e1, s);
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = WDG_EHIP;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (best == 0.0f || ms < best)) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(src);
+    (void)hipFree(dst);
+    if (rc != WDG_OK) return rc;
+    *gbs = 2.0 * static_cast<double>(bytes) / (static_cast<double>(best) * 1e-3) / 1e9;
     return WDG_OK;
 }

@@ -35,6 +35,7 @@ _lib = C.CDLL(LIB_PATH)
 WDG_OK, WDG_EINVAL, WDG_EMESH, WDG_ENOMEM, WDG_EHIP, WDG_ESTATE, WDG_EPROBE, WDG_ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 WDG_FP64, WDG_FP32 = 0, 1
 WDG_HOST_ONLY = 1
+WDG_ALIGN_COMPONENTS = 2
 WDG_OP_DR, WDG_OP_DS, WDG_OP_DT, WDG_OP_LIFT, WDG_OP_VQ, WDG_OP_PQ, WDG_OP_M = range(7)
 WDG_KERNEL_AUTO, WDG_KERNEL_SCALAR, WDG_KERNEL_MFMA = 0, 1, 2
 WDG_PML_WAA, WDG_PML_DIRECT, WDG_PML_CONSTANT = 0, 1, 2
@@ -114,8 +115,11 @@ wdg_memory_report = _sig("wdg_memory_report", C.c_int32, _ctx, C.POINTER(wdg_mem
 wdg_set_tiles = _sig("wdg_set_tiles", C.c_int32, _ctx, C.c_int32)
 wdg_set_waa_shortcut = _sig("wdg_set_waa_shortcut", C.c_int32, _ctx, C.c_int32)
 wdg_set_schedule = _sig("wdg_set_schedule", C.c_int32, _ctx, C.c_int32)
+wdg_element_slots = _sig("wdg_element_slots", C.c_int32, _ctx, C.POINTER(C.c_int32))
+wdg_set_step_groups = _sig("wdg_set_step_groups", C.c_int32, _ctx, C.c_int32, C.POINTER(C.c_int32))
 wdg_autotune_cached = _sig("wdg_autotune_cached", C.c_int32, _ctx, C.c_int32, C.c_void_p, C.POINTER(C.c_int32))
 wdg_energy_noalloc = _sig("wdg_energy_noalloc", C.c_int32, _ctx, C.c_void_p, C.c_void_p)
+wdg_measure_copy_bandwidth = _sig("wdg_measure_copy_bandwidth", C.c_int32, C.c_int64, C.c_void_p, _dp)
 wdg_measure_mfma_peak = _sig("wdg_measure_mfma_peak", C.c_int32, C.c_int32, C.c_int32, C.c_void_p, _dp)
 wdg_autotune = _sig("wdg_autotune", C.c_int32, _ctx, C.c_int32, _dp, C.c_void_p)
 wdg_step_graph = _sig("wdg_step_graph", C.c_int32, _ctx, C.c_double, C.c_int32, C.c_void_p)
@@ -195,9 +199,10 @@ def make_mesh(vxyz, etov, vertex_id=None):
 class Context:
     """Owns a wdg_ctx; host-only contexts need no GPU."""
 
-    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, host_only=False, vertex_id=None):
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, host_only=False, vertex_id=None,
+                 flags=0):
         mesh = make_mesh(vxyz, etov, vertex_id)
-        meth = make_method(N, rule, pml, alpha, precision, WDG_HOST_ONLY if host_only else 0)
+        meth = make_method(N, rule, pml, alpha, precision, (WDG_HOST_ONLY if host_only else 0) | int(flags))
         h = _ctx()
         _check(wdg_create(C.byref(mesh), C.byref(meth), C.byref(h)))
         self.h = h
@@ -208,6 +213,12 @@ class Context:
         if h and wdg_destroy is not None:
             wdg_destroy(h)
             self.h = None
+
+    def element_slots(self):
+        """Device slot (block * 64 + lane) of every element, [K] int32."""
+        out = np.zeros(self.dims.K, dtype=np.int32)
+        _check(wdg_element_slots(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))), self.h)
+        return out
 
     def get_dims(self):
         d = wdg_dims_t()
@@ -278,8 +289,9 @@ class Context:
 class Simulation(Context):
     """A device context whose three state buffers are PyTorch CUDA (HIP) tensors."""
 
-    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, device="cuda", vertex_id=None):
-        super().__init__(vxyz, etov, N, rule, pml, alpha, precision, host_only=False, vertex_id=vertex_id)
+    def __init__(self, vxyz, etov, N, rule, pml, alpha=1.0, precision=WDG_FP64, device="cuda", vertex_id=None,
+                 flags=0):
+        super().__init__(vxyz, etov, N, rule, pml, alpha, precision, host_only=False, vertex_id=vertex_id, flags=flags)
         nbytes = self.dims.state_bytes
         self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=device) for _ in range(3)]
         _check(wdg_bind_state(self.h, C.c_void_p(self.bufs[0].data_ptr()), C.c_void_p(self.bufs[1].data_ptr()),
@@ -361,6 +373,15 @@ class Simulation(Context):
         _check(wdg_set_tiles(self.h, int(tiles)), self.h)
         self.dims = self.get_dims()
 
+    def set_step_groups(self, group, ngroups=None):
+        """Groups of independent simulations for captured stepping (group [K] int, or None to remove)."""
+        if group is None:
+            _check(wdg_set_step_groups(self.h, 0, None), self.h)
+            return
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        n = int(g.max()) + 1 if ngroups is None else int(ngroups)
+        _check(wdg_set_step_groups(self.h, n, g.ctypes.data_as(C.POINTER(C.c_int32))), self.h)
+
     def set_schedule(self, reversed_order):
         _check(wdg_set_schedule(self.h, int(bool(reversed_order))), self.h)
 
@@ -426,6 +447,16 @@ def measure_mfma_peak(precision, iters=4000, stream=None):
     rc = wdg_measure_mfma_peak(int(precision), int(iters), st, C.byref(out))
     if rc != WDG_OK:
         raise WdgError(rc, f"wdg_measure_mfma_peak failed ({rc})")
+    return out.value
+
+
+def measure_copy_bandwidth(nbytes=1 << 30, stream=None):
+    """GB/s (read + written) of the library's plain device copy of nbytes bytes."""
+    out = C.c_double(0.0)
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = wdg_measure_copy_bandwidth(int(nbytes), st, C.byref(out))
+    if rc != WDG_OK:
+        raise WdgError(rc, f"wdg_measure_copy_bandwidth failed ({rc})")
     return out.value
 
 

@@ -119,6 +119,38 @@ def test_autotune_cache_and_environment_overrides(wdg, tmp_path, monkeypatch):
         make()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grouped_capture_is_bitwise_equal(wdg, precision):
+    """Step groups (aligned components, both steps of a pair group after group) change no bit of any field."""
+    from paper_2006_02551_amd.batch import Batch
+    cfg = inputs.config("c4", batch={"nsim": 6, "n_range": [3, 6], "sigma_range": [10.0, 50.0], "orders": [2, 3, 4],
+                                     "seed": 2})
+    _say(f"grouped capture, precision {precision}")
+    plain = Batch(cfg, precision)
+    grouped = Batch(cfg, precision, group_mb=1.0)
+    assert grouped.step_groups is not None and grouped.step_groups.max() >= 2  # several groups
+    q0 = plain.initial_fields()
+    assert np.array_equal(q0, grouped.initial_fields())
+    for b in (plain, grouped):
+        b.set_fields(q0)
+    plain.step(10, graph=False)   # eager, one launch per stage over every block
+    grouped.step(10, graph=True)  # captured, group after group
+    assert np.array_equal(grouped.sim.get_fields(), plain.sim.get_fields())
+    grouped.step(3, graph=True)   # an odd last step runs eagerly
+    plain.step(3, graph=True)
+    assert np.array_equal(grouped.sim.get_fields(), plain.sim.get_fields())
+    d = grouped.sim.get_dims()
+    assert d.steps == 13
+    # groups must not split a simulation, and need an aligned context
+    bad = grouped.step_groups[grouped.group].copy()
+    bad[0] = bad[-1]
+    with pytest.raises(wdg.WdgError):
+        grouped.sim.set_step_groups(bad)
+    with pytest.raises(wdg.WdgError) as e:
+        plain.sim.set_step_groups(np.zeros(plain.K, np.int32))
+    assert e.value.code == wdg.WDG_ESTATE
+
+
 def test_graph_replay_matches_eager(wdg):
     import torch
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1})

@@ -177,6 +177,36 @@ def test_pml_profile_resampling_matches_oracle():
     assert np.max(np.abs(ctx.get_sigma_q() - osim.op.sigma)) <= 1e-13 * max(pml["sigma_max"])
 
 
+def test_aligned_components_layout():
+    """WDG_ALIGN_COMPONENTS: every simulation of a concatenated batch starts at a block boundary of each class, no
+    block holds elements of two simulations, and the per-element setup is unchanged."""
+    cfg = inputs.config("c4", batch={"nsim": 5, "n_range": [2, 4], "sigma_range": [10.0, 50.0], "orders": [2, 3],
+                                     "seed": 3})
+    recipe = inputs.batch_recipe(cfg["batch"])
+    meshes = inputs.batch_meshes(cfg, recipe)
+    vx, ev, group, offsets = inputs.concat_meshes(meshes)
+    rule = inputs.load_rule(cfg["cub_degree"])
+    plain = wdg.Context(vx, ev, cfg["N"], rule, cfg["pml"], host_only=True)
+    al = wdg.Context(vx, ev, cfg["N"], rule, cfg["pml"], host_only=True, flags=wdg.WDG_ALIGN_COMPONENTS)
+    d, B = al.dims, al.dims.block
+    slots = al.element_slots()
+    assert len(np.unique(slots)) == d.K and slots.min() >= 0 and slots.max() < d.nblk * B
+    blk = slots // B
+    owner = {}
+    for k in range(d.K):
+        assert owner.setdefault(int(blk[k]), int(group[k])) == int(group[k])  # one simulation per block
+    pml = blk < d.nblk_pml
+    for i in range(len(meshes)):
+        for cls in (pml, ~pml):
+            sel = np.nonzero((group == i) & cls)[0]
+            if len(sel):
+                assert slots[sel].min() % B == 0  # starts at a block boundary
+                assert blk[sel].max() - blk[sel].min() + 1 == (len(sel) + B - 1) // B  # contiguous, dense
+    assert d.nblk >= plain.dims.nblk and d.K_pml == plain.dims.K_pml
+    assert np.array_equal(al.node_coords(), plain.node_coords())
+    assert np.array_equal(al.get_sigma_q(), plain.get_sigma_q())
+
+
 def test_loss_gradient_needs_device_state():
     cfg = inputs.config("c1")
     ctx, *_ = _ctx(cfg)
