@@ -29,12 +29,14 @@ PML schemes, N = 1..4) and the precision form at full size (`precision_form`: 38
 FP32).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--stepping-only]
-                       [--table-i-only] [--copy-calibration MIB]
+                       [--table-i-only | --adjoint-only | --precision-form-only [--pf-steps K] | --batch-only]
+                       [--copy-calibration MIB]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -224,8 +226,21 @@ def run_adjoint(precision):
     t0 = time.perf_counter()
     J, _, gp = sim.loss_gradient(dt, steps, cfg["shell"])
     ms_adj = (time.perf_counter() - t0) * 1e3
+    # the same with two checkpoint segments (half the steps recomputed; 2 + 5 ceil(T/2) + 5 state buffers, about
+    # 103 GB in FP64: the memory of one MI355X buys back half of the recomputation)
+    half = (steps + 1) // 2
+    sim.set_fields(q0)
+    sim.set_time(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J2, _, _ = sim.loss_gradient(dt, steps, cfg["shell"], half)
+    ms_half = (time.perf_counter() - t0) * 1e3
+    assert J2 == J
     del sim
     return {"ratio": ms_adj / ms_fwd, "ms_forward": ms_fwd, "ms_loss_gradient": ms_adj, "loss": J,
+            "checkpoint_interval": int(math.ceil(math.sqrt(steps))),
+            "ratio_two_segments": ms_half / ms_fwd, "ms_loss_gradient_two_segments": ms_half,
+            "two_segments_state_buffers": 2 + 5 * half + 5,
             "dJ_dsigma_max": list(gp[:3]), "dJ_dL": list(gp[3:6]), "dJ_dorder": gp[6]}
 
 

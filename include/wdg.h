@@ -420,8 +420,11 @@ int32_t wdg_shell_energy(wdg_ctx* ctx, const wdg_shell* shell, double* out, void
  *                parameters describe).
  * The state advances by nsteps steps exactly as with wdg_step (no probe rows).
  * Forward states are checkpointed every checkpoint_interval steps (0:
- * ceil(sqrt(nsteps))); device memory for ceil(nsteps / interval) + 5 interval
- * + 7 state buffers is allocated and freed inside the call.  Needs kappa = 1
+ * ceil(sqrt(nsteps))) and every segment but the last is recomputed once during
+ * the reverse sweep (the forward sweep keeps the last segment's stage inputs);
+ * device memory for ceil(nsteps / interval) + 5 interval + 5 state buffers is
+ * allocated and freed inside the call (a larger interval trades memory for
+ * less recomputation: interval = nsteps recomputes nothing).  Needs kappa = 1
  * and an order and rule with a matrix-core kernel (WDG_EINVAL otherwise: FP64
  * at N = 4, N = 3 with more than 32 cubature points in FP64).  Synchronous. */
 int32_t wdg_loss_gradient(wdg_ctx* ctx, double dt, int32_t nsteps, const wdg_shell* shell,

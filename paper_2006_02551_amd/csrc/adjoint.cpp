@@ -266,7 +266,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         DevBuf acc, ckpt, stages, qh, y, rtmp, grad;
         int yc = 0;  // current half of y
         acc.alloc(sizeof(double));
-        ckpt.alloc(static_cast<size_t>(std::max(nseg, 1)) * bytes);
+        ckpt.alloc(static_cast<size_t>(nseg - 1) * bytes);  // the last segment keeps its stage inputs instead
         stages.alloc(static_cast<size_t>(5 * std::min(C, std::max(nsteps, 1)) + 1) * bytes);
         qh.alloc(2 * bytes);
         y.alloc(2 * bytes);
@@ -278,22 +278,43 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         auto yb = [&](int i) { return static_cast<char*>(y.p) + static_cast<size_t>(i) * bytes; };
         hip_check(hipMemsetAsync(acc.p, 0, sizeof(double), s), "clear");
 
-        // ---- forward sweep: the context's state advances; checkpoints and the loss
+        // ---- forward sweep: the context's state advances; checkpoints and the loss.  The last segment's
+        // stage inputs are written straight into the stage buffers, so the reverse sweep does not
+        // recompute that segment (the same launches on the same inputs as a recomputation)
         const double t0 = c->t;
+        const int last0 = (nseg - 1) * C;  // first step of the last segment
         for (int n = 0; n < nsteps; ++n) {
-            if (n % C == 0)
-                hip_check(hipMemcpyAsync(static_cast<char*>(ckpt.p) + static_cast<size_t>(n / C) * bytes, c->q[c->cur], bytes,
-                                         hipMemcpyDeviceToDevice, s),
-                          "checkpoint");
+            if (n < last0) {
+                if (n % C == 0)
+                    hip_check(hipMemcpyAsync(static_cast<char*>(ckpt.p) + static_cast<size_t>(n / C) * bytes, c->q[c->cur],
+                                             bytes, hipMemcpyDeviceToDevice, s),
+                              "checkpoint");
+                for (int i = 0; i < 5; ++i) {
+                    const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[i], kRkB[i], dt,
+                                                   c->t + kRkC[i] * dt, i > 0, s);
+                    if (rc != WDG_OK) return rc;
+                    c->cur = 1 - c->cur;
+                }
+                c->t += dt;
+                c->steps += 1;
+                shell_energy_into(c, sd, c->q[c->cur], 0.5 * dt, static_cast<double*>(acc.p), s);
+                continue;
+            }
+            const int j = n - last0;
+            if (j == 0) hip_check(hipMemcpyAsync(st(0), c->q[c->cur], bytes, hipMemcpyDeviceToDevice, s), "checkpoint");
             for (int i = 0; i < 5; ++i) {
-                const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[i], kRkB[i], dt,
+                const int rc = launch_stage_on(c, st(5 * j + i), st(5 * j + i + 1), c->res, kRkA[i], kRkB[i], dt,
                                                c->t + kRkC[i] * dt, i > 0, s);
                 if (rc != WDG_OK) return rc;
-                c->cur = 1 - c->cur;
             }
             c->t += dt;
             c->steps += 1;
-            shell_energy_into(c, sd, c->q[c->cur], 0.5 * dt, static_cast<double*>(acc.p), s);
+            shell_energy_into(c, sd, st(5 * (j + 1)), 0.5 * dt, static_cast<double*>(acc.p), s);
+        }
+        if (nsteps > last0) {  // the final state back into the context's buffers, where stepping leaves it
+            const int m = nsteps - last0;
+            if ((5 * m) % 2) c->cur = 1 - c->cur;
+            hip_check(hipMemcpyAsync(c->q[c->cur], st(5 * m), bytes, hipMemcpyDeviceToDevice, s), "final state");
         }
 
         // ---- adjoint sweep, segment by segment from the last
@@ -302,11 +323,13 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         int hc = 0;
         for (int seg = nseg - 1; seg >= 0; --seg) {
             const int n0 = seg * C, m = std::min(nsteps, n0 + C) - n0;
-            hip_check(hipMemcpyAsync(st(0), static_cast<char*>(ckpt.p) + static_cast<size_t>(seg) * bytes, bytes,
-                                     hipMemcpyDeviceToDevice, s),
-                      "restore");
+            // the last segment's stage inputs are already in the stage buffers (forward sweep)
+            if (seg != nseg - 1)
+                hip_check(hipMemcpyAsync(st(0), static_cast<char*>(ckpt.p) + static_cast<size_t>(seg) * bytes, bytes,
+                                         hipMemcpyDeviceToDevice, s),
+                          "restore");
             double t = t0 + n0 * dt;
-            for (int jstep = 0; jstep < m; ++jstep) {
+            for (int jstep = 0; jstep < (seg == nseg - 1 ? 0 : m); ++jstep) {
                 for (int i = 0; i < 5; ++i) {
                     const int rc = launch_stage_on(c, st(5 * jstep + i), st(5 * jstep + i + 1), rtmp.p, kRkA[i], kRkB[i], dt,
                                                    t + kRkC[i] * dt, i > 0, s);

@@ -137,9 +137,15 @@ def test_checkpoint_interval_and_empty_shell(wdg):
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
     _say("checkpoint intervals")
     res = []
-    for interval in (1, 3, 0, 20):
+    plain, osim, q0 = _pair(wdg, cfg, 0)
+    plain.step(osim.dt, 10)
+    want = plain.get_fields()
+    for interval in (1, 3, 0, 7, 20):  # 20: one segment, nothing recomputed
         sim, osim, q0 = _pair(wdg, cfg, 0)
         res.append(sim.loss_gradient(osim.dt, 10, SHELL_C1, interval))
+        # the state advances exactly as plain stepping (bitwise), whichever segment kept its stage inputs
+        assert np.array_equal(sim.get_fields(), want), interval
+        assert sim.get_dims().steps == 10
     for J, g, gp in res[1:]:
         assert J == res[0][0]  # the forward sweep is deterministic
         assert np.max(np.abs(g - res[0][1])) <= 1e-13 * np.max(np.abs(res[0][1]))
