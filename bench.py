@@ -204,6 +204,7 @@ def run_adjoint(precision):
     cfg = inputs.config("c5")
     vx, ev = inputs.mesh_for(cfg)
     rule = inputs.load_rule(cfg["cub_degree"])
+    torch.cuda.empty_cache()  # the two-segment run allocates ~100 GB of state buffers in the library
     sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
     q0 = inputs.gaussian_fields(cfg, sim.node_coords())
     dt = cfg["cfl"] * sim.dims.dt_unit

@@ -211,8 +211,10 @@ struct Shape {
 // flux parameter negated by the caller.
 //
 // NQ > 0 fixes the number of cubature points at compile time (the stored rules of degree 2N), so that
-// the guards on padded cubature slots resolve at compile time; NQ = 0 reads it from p.Nq.
-template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW, int NQ, int MODE = kPmlWaa>
+// the guards on padded cubature slots resolve at compile time; NQ = 0 reads it from p.Nq.  RR = false is
+// the form of the first Runge-Kutta stage (A_1 = 0): it reads no residual at all (the other forms read it
+// when p.read_res is set).
+template <typename real, int N, int QT, bool KAPPA, bool ADJ, int TPW, int NQ, int MODE = kPmlWaa, bool RR = true>
 __global__ __launch_bounds__(TPW * kMfmaThreads) __attribute__((amdgpu_waves_per_eu(Shape<real, N, QT, ADJ, TPW>::WAVES_PER_SIMD)))
 void stage_mfma_kernel(StageParams p) {
     static_assert(!(ADJ && KAPPA), "the adjoint stage is written for kappa = 1");
@@ -339,7 +341,7 @@ void stage_mfma_kernel(StageParams p) {
     // auxiliary fields entering the PML terms (forward: q_in; adjoint: y)
     const real* __restrict__ qb = ADJ ? static_cast<const real*>(p.q_base) : qin;
     const real* __restrict__ pin = ADJ ? static_cast<const real*>(p.res) : qin;
-    const bool read_res = p.read_res != 0;
+    const bool read_res = RR && p.read_res != 0;
     real bp[SP];
     real rP[PT][4], qP[PT][4], rE[PT][4];  // adjoint: qP, rE hold the update base (FP64)
 #pragma unroll
@@ -364,7 +366,7 @@ void stage_mfma_kernel(StageParams p) {
                 const int nd = node < Np ? node : 0;
                 const unsigned lo = static_cast<unsigned>(j + nd * B);
                 if (((0 * PT + t) * 4 + v) / UPS == s)
-                    rP[t][v] = GATHER_ALL ? ldg(rs + (pml ? pbase : ebase), lo)
+                    rP[t][v] = GATHER_ALL ? (RR ? ldg(rs + (pml ? pbase : ebase), lo) : real(0))
                                           : ((!ADJ && !DIRECT && pml && read_res) ? ldg(rs + pbase, lo) : real(0));
                 // (the adjoint reads its update base where it is used: fewer registers live through the
                 // curl and the PML terms, no spills)
@@ -689,7 +691,7 @@ void stage_mfma_kernel(StageParams p) {
                 for (int v = 0; v < 4; ++v) {
                     const int node = 16 * t + 4 * v + g;
                     const int nd = node < Np ? node : 0;
-                    rE[t][v] = GATHER_ALL ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B))
+                    rE[t][v] = GATHER_ALL ? (RR ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B)) : real(0))
                                           : ((read_res && !(DIRECT && pml)) ? ldg(rs + ebase, static_cast<unsigned>(j + nd * B)) : real(0));
                 }
         }
@@ -827,7 +829,10 @@ int launch_t(const StageParams& p, hipStream_t s) {
         constexpr int RQ = rule_nq<N>();
         if constexpr (MODE == kPmlWaa && !K && (RQ + 15) / 16 == QT) {
             if (p.Nq == RQ) {
-                hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
+                if (!ADJ && !p.read_res)  // the first Runge-Kutta stage: no residual loads
+                    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ, kPmlWaa, false>), grid, block, 0, s, p);
+                else
+                    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
                 return static_cast<int>(hipGetLastError());
             }
         }
