@@ -71,12 +71,30 @@ struct Mma<double> {
         return c;
     }
 };
+// FP32: nv = 4 is one V_MFMA_F32_16X16X4_F32; nv < 4 marks a step whose rows all lie in the first four of
+// the tile, run as one V_MFMA_F32_4X4X1_16B_F32 (a third of the cycles).  Its sixteen blocks are the
+// (k, 4-column group) pairs of the step: lane 16 k + 4 c + n holds B[k][4 c + n] exactly as the 16x16x4
+// product wants it, the lane's A word is row i = lane % 4 of column k, and the result register i of that
+// lane accumulates row i's partial sum over the columns k of every step.  fold() adds the four partials and
+// moves row g to register 0 of lane group g, the 16x16x4 result layout.
 template <>
 struct Mma<float> {
     using v4 = v4f;
     using AF = float;
-    static __device__ __forceinline__ v4 run(AF a, float b, v4 c, int = 4) {
+    static __device__ __forceinline__ v4 run(AF a, float b, v4 c, int nv = 4) {
+        if (nv < 4) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ v4 fold(v4 d, int g) {
+        v4 s;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float x = d[r];
+            x += __shfl_xor(x, 16);
+            x += __shfl_xor(x, 32);
+            s[r] = x;
+        }
+        return v4{g == 0 ? s[0] : g == 1 ? s[1] : g == 2 ? s[2] : s[3], 0.0f, 0.0f, 0.0f};
     }
 };
 
@@ -389,6 +407,13 @@ void stage_mfma_kernel(StageParams p) {
     constexpr int NVL = S::NVL;
     const int lq = 4 * (lane & 3) + ((lane & 15) >> 2);
     const int lp = (lane >> 4) * MR + (lq < MR ? lq : MR - 1);  // FP32: lane's word in a compact tile
+    // FP32 4x4x1 steps on the last node tile (at most 4 rows) and the last cubature tile (at most 4 points,
+    // compile-time rule size), weight-adjusted mode: the lane's A word is row lane % 4, column lane / 16
+    constexpr int QR = NQ > 0 ? NQ - 16 * (QT - 1) : 16;
+    constexpr bool SMALLN = !F64 && MODE == kPmlWaa && MR <= 4;
+    constexpr bool SMALLQ = !F64 && MODE == kPmlWaa && NQ > 0 && QR <= 4;
+    const int ls = (lane >> 4) * MR + ((lane & 3) < MR ? (lane & 3) : MR - 1);  // ... in the compact tile
+    const int lsq = (lane >> 4) * 16 + 4 * (lane & 3);                          // ... in a full V_q tile
     const int l4 = (lane >> 4) * 16 + (lane & 3) * 4;             // FP64: lane's first word in a full tile
     const int l4c = (lane >> 4) * 4 * NVL + (lane & 3) * NVL;     // FP64: ... in a compact tile
     auto frag = [&](int off, int t, int s, int K) -> AF {
@@ -403,7 +428,8 @@ void stage_mfma_kernel(StageParams p) {
             for (int v = 0; v < NVL; ++v) a[v] = p[v];
             return a;
         } else {
-            return t < PT - 1 ? fr[off + (t * K + s) * 64 + lane] : fr[off + (PT - 1) * K * 64 + s * 4 * MR + lp];
+            if (t < PT - 1) return fr[off + (t * K + s) * 64 + lane];
+            return fr[off + (PT - 1) * K * 64 + s * 4 * MR + (SMALLN ? ls : lp)];
         }
     };
     auto fragq = [&](int t, int s) -> AF {
@@ -411,14 +437,21 @@ void stage_mfma_kernel(StageParams p) {
             const real* p = fr + OFF_VQ + (t * SP + s) * 64 + l4;
             return AF{p[0], p[1], p[2], p[3]};
         } else {
-            return fr[OFF_VQ + (t * SP + s) * 64 + lane];
+            return fr[OFF_VQ + (t * SP + s) * 64 + ((SMALLQ && t == QT - 1) ? lsq : lane)];
         }
     };
-    // row groups with valid rows in node tile t and cubature tile t (FP64 skips the others)
-    auto nvn = [&](int t) -> int { return t < PT - 1 ? 4 : NVL; };
+    // FP64: row groups with valid rows in node tile t and cubature tile t (the others are skipped); FP32: 1
+    // for a 4x4x1 tile, else 4
+    auto nvn = [&](int t) -> int { return F64 ? (t < PT - 1 ? 4 : NVL) : ((SMALLN && t == PT - 1) ? 1 : 4); };
     auto nvq = [&](int t) -> int {
+        if constexpr (!F64) return (SMALLQ && t == QT - 1) ? 1 : 4;
         const int rows = (NQ > 0 ? NQ : QMAX) - 16 * t;
         return rows >= 16 ? 4 : (rows + 3) / 4;
+    };
+    // FP32 4x4x1 accumulators to the 16x16x4 layout (FP64: unchanged)
+    auto fold = [&](v4 d) -> v4 {
+        if constexpr (F64) return d;
+        else return M::fold(d, g);
     };
     auto ehv = [&](int c, int node) -> real { return eh[(c * Np + node) * T + j]; };
 
@@ -601,6 +634,14 @@ void stage_mfma_kernel(StageParams p) {
                     VPf = M::run(a, ok ? fp[s] : real(0), VPf, nvq(tq));
                 }
             }
+            if (SMALLQ && tq == QT - 1) {
+                VF = fold(VF);
+                VP = fold(VP);
+                if constexpr (ADJ) {
+                    VFf = fold(VFf);
+                    VPf = fold(VPf);
+                }
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int q = 16 * tq + 4 * v + g;
@@ -654,6 +695,7 @@ void stage_mfma_kernel(StageParams p) {
                 }
             }
         }
+        if constexpr (SMALLN) RP[PT - 1] = fold(RP[PT - 1]);
         aux_update(RP);
     }
 
@@ -698,6 +740,9 @@ void stage_mfma_kernel(StageParams p) {
         if constexpr (S::SGFL) __syncthreads();  // every wave has read sigma from the flux buffer
         flux_and_lift();
     }
+
+    // every product into R is done: its 4x4x1 tile to the 16x16x4 layout
+    if constexpr (SMALLN) R[PT - 1] = fold(R[PT - 1]);
 
     // ---- dipole source on the electric components (not part of the adjoint operator)
     if (!ADJ && u < 3) {
@@ -750,6 +795,7 @@ void stage_mfma_kernel(StageParams p) {
                     for (int t = 0; t < QT; ++t) Z[t] = M::run(fragq(t, sp), R[tp][v], Z[t], nvq(t));
                 }
             }
+        if constexpr (SMALLQ) Z[QT - 1] = fold(Z[QT - 1]);
         if (KAPPA) {
             const real* __restrict__ kp = static_cast<const real*>(p.kappa) + static_cast<size_t>(blk) * 3 * Nq * B + e;
 #pragma unroll
@@ -776,6 +822,7 @@ void stage_mfma_kernel(StageParams p) {
                     for (int t = 0; t < PT; ++t) O[t] = M::run(frag(OFF_PQ, t, sq, SQM), Z[tq][v], O[t], nvn(t));
                 }
             }
+        if constexpr (SMALLN) O[PT - 1] = fold(O[PT - 1]);
 #pragma unroll
         for (int t = 0; t < PT; ++t) R[t] = O[t];
     }
@@ -829,10 +876,12 @@ int launch_t(const StageParams& p, hipStream_t s) {
         constexpr int RQ = rule_nq<N>();
         if constexpr (MODE == kPmlWaa && !K && (RQ + 15) / 16 == QT) {
             if (p.Nq == RQ) {
-                if (!ADJ && !p.read_res)  // the first Runge-Kutta stage: no residual loads
-                    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ, kPmlWaa, false>), grid, block, 0, s, p);
-                else
-                    hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
+                bool first = false;  // the first Runge-Kutta stage of the forward scheme: no residual loads
+                if constexpr (!ADJ) first = !p.read_res;
+                if constexpr (!ADJ) {
+                    if (first) hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ, kPmlWaa, false>), grid, block, 0, s, p);
+                }
+                if (!first) hipLaunchKernelGGL((stage_mfma_kernel<real, N, QT, K, ADJ, TPW, RQ>), grid, block, 0, s, p);
                 return static_cast<int>(hipGetLastError());
             }
         }
