@@ -18,9 +18,10 @@ Roofline: algorithmic bytes and flops per stage launch (see
 `algorithmic_traffic`) over the average launch time of the timed region
 (HIP events on the launch stream; the per-step probe launch is included, so
 the figure is slightly conservative), against the vendor peaks and against
-peaks measured on the same GPU (`measured_peaks`: a 1 GiB device copy and the
-16x16x4 MFMA rate); the bound is whichever of bytes / bandwidth and flops /
-peak is larger.
+peaks measured on the same GPU (`measured_peaks`: a 1 GiB device copy and
+chains of the MFMA instructions the kernel issues); the bound is whichever of
+bytes / bandwidth and flops / peak is larger. `traffic` is the counted
+memory-side bytes per launch (`MEASURED_TRAFFIC`).
 
 Also reported: the adjoint/forward wall-time ratio of the loss gradient (`adjoint_forward_ratio`), the
 batching form's throughput (`batch`: 32 independent simulations in one context), the Table I contrast
@@ -45,13 +46,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-# HBM bytes per stage launch from rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00
-# (scale factors from a 1 GiB device copy), taken on the kernel source with
-# this sha256; reported only while the source is unchanged.
+# Memory-side bytes per stage launch from rocprofv3's TCC_EA0 request-size counters (reads: 32 B x RDREQ_32B +
+# 64 B x RDREQ_64B + 128 B x RDREQ_128B; writes: 64 B x WRREQ_64B + 32 B x the other WRREQ), one pass for
+# the reads and one for the writes. The same counters read 1.000 x 1 GiB each way for the library's 1 GiB
+# device copy, so no scale factor is applied. Per kernel: (first stage of a step, which reads no residual;
+# each of the other four stages), reads and writes in bytes; a launch's figure is the five-stage average.
+# Taken on the kernel sources with this sha256 (kernels_mfma.hip + device.hpp); reported only while they are
+# unchanged.
 MEASURED_TRAFFIC = {
-    "source_sha256": "5f0c59752698f274694e27d1e5b57bc3449da74e08ba50480c016eef50dd7f21",
-    "stage_mfma_kernel<double,N=3,Nq=24>": (129871.8 * 2.0 + 160560.0) * 1024,
-    "stage_mfma_kernel<float,N=3,Nq=24>": (60093.8 * 2.0 + 91153.0) * 1024,
+    "source_sha256": "0ba3f8879da7140b2df9fd54152bbc2e0aaae40b11d61b894b6e5f795b16a370",
+    "stage_mfma_kernel<double,N=3,Nq=24>": {"read": (179176390, 265403898), "write": (164413440, 164413440)},
+    "stage_mfma_kernel<float,N=3,Nq=24>": {"read": (87836256, 131307286), "write": (90165376, 91789517)},
+    "stage_mfma_kernel<double,N=4,Nq=51>": {"read": (2579232174, 3781003632), "write": (2226524160, 2226524160)},
+    "stage_mfma_kernel<float,N=4,Nq=51>": {"read": (1278044270, 1906668094), "write": (1178140069, 1252153093)},
 }
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)
@@ -110,7 +117,8 @@ def roofline(bytes_per_launch, flops_per_launch, launch_us, word, peaks=None, tr
 
 def measured_peaks():
     """Peaks measured on this GPU: a 1 GiB device-to-device copy (bytes read + written over the time) and the
-    sustained 16x16x4 MFMA rate in FP64 and FP32 (the library's microbenchmark)."""
+    sustained MFMA rate in FP64 (four-block 4x4x4, as the stage kernel issues it) and FP32 (16x16x4), from the
+    library's microbenchmarks."""
     import torch
 
     from paper_2006_02551_amd import wdg
@@ -140,12 +148,16 @@ def measured_peaks():
 
 
 def measured_traffic(kernel):
+    """Counted bytes per launch of `kernel` (five-stage average), or None once its sources have changed."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2006_02551_amd", "csrc", "kernels_mfma.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != MEASURED_TRAFFIC["source_sha256"]:
-            return None
-    return MEASURED_TRAFFIC.get(kernel)
+    h = hashlib.sha256()
+    for name in ("kernels_mfma.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2006_02551_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != MEASURED_TRAFFIC["source_sha256"] or kernel not in MEASURED_TRAFFIC:
+        return None
+    m = MEASURED_TRAFFIC[kernel]
+    return sum((first + 4 * rest) / 5 for first, rest in (m["read"], m["write"]))
 
 
 def run_gpu(cfg, precision, steps, warmup, shortcut=False, peaks=None):
