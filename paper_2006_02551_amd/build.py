@@ -23,8 +23,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdg.so")
 ARCH = "gfx950"
 
-SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "batch.cpp", "pml_schemes.cpp", "kernels.hip", "kernels_mfma.hip",
-           "kernels_adjoint.hip", "peak.hip", "noalloc.hip"]
+SOURCES = ["refel.cpp", "mesh.cpp", "api.cpp", "adjoint.cpp", "batch.cpp", "pml_schemes.cpp", "trace.cpp", "kernels.hip",
+           "kernels_mfma.hip", "kernels_adjoint.hip", "peak.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", f"-I{os.path.join(HERE, '..', 'include')}"]
 # Packed FP32 instructions are disabled for all device code.

@@ -255,6 +255,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
     if (!adjoint_supported(S.ref.N, S.ref.Nq, c->precision))
         return fail(c, WDG_EINVAL, "no adjoint kernel for this order, rule size and precision");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceRange range("wdg_loss_gradient");
     return guarded(c, [&]() -> int {
         const int Nq = S.ref.Nq, B = S.B;
         const size_t bytes = static_cast<size_t>(c->state_elems) * c->rsize;
@@ -284,6 +285,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         const double t0 = c->t;
         const int last0 = (nseg - 1) * C;  // first step of the last segment
         for (int n = 0; n < nsteps; ++n) {
+            TraceRange fstep("forward step");
             if (n < last0) {
                 if (n % C == 0)
                     hip_check(hipMemcpyAsync(static_cast<char*>(ckpt.p) + static_cast<size_t>(n / C) * bytes, c->q[c->cur],
@@ -322,6 +324,7 @@ int32_t wdg_loss_gradient(wdg_ctx* c, double dt, int32_t nsteps, const wdg_shell
         hip_check(hipMemsetAsync(grad.p, 0, ngrad * sizeof(double), s), "clear");
         int hc = 0;
         for (int seg = nseg - 1; seg >= 0; --seg) {
+            TraceRange aseg("adjoint segment");
             const int n0 = seg * C, m = std::min(nsteps, n0 + C) - n0;
             // the last segment's stage inputs are already in the stage buffers (forward sweep)
             if (seg != nseg - 1)

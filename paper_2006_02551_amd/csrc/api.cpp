@@ -581,8 +581,10 @@ int32_t wdg_step(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) {
     if (int e = check_state(c)) return e;
     if (c->nprobe > 0 && c->probe_rows + nsteps > c->probe_cap) return fail(c, WDG_EPROBE, "probe buffer would overflow");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceRange range("wdg_step");
     return guarded(c, [&]() -> int {
         for (int n = 0; n < nsteps; ++n) {
+            TraceRange step("step");
             for (int i = 0; i < 5; ++i) {
                 const int rc = launch_stage_on(c, c->q[c->cur], c->q[1 - c->cur], c->res, kRkA[i], kRkB[i], dt,
                                                c->t + kRkC[i] * dt, i > 0, s);

@@ -254,6 +254,7 @@ int32_t wdg_step_graph(wdg_ctx* c, double dt, int32_t nsteps, void* hip_stream) 
     if (c->has_src) return fail(c, WDG_EINVAL, "graph stepping needs no source (its amplitude changes every stage)");
     if (c->nprobe > 0) return fail(c, WDG_EINVAL, "graph stepping needs no probes");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceRange range("wdg_step_graph");
     return guarded(c, [&]() -> int {
         const int pairs = nsteps / 2;
         if (pairs > 0) {

@@ -12,6 +12,7 @@
 #include "../../include/wdg.h"
 #include "device.hpp"
 #include "host.hpp"
+#include "trace.hpp"
 
 namespace wdg {
 
