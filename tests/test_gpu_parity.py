@@ -315,6 +315,30 @@ def test_edge_cases(wdg):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_watchdog_after_a_time_step_beyond_the_stability_bound(wdg, precision):
+    """The vacuum cavity of the oracle's stability pin: at the dt rule the library follows the oracle and the
+    energy stays below its start; at fifty times that step the fields overflow and the energy readout returns
+    WDG_ENONFINITE (every kernel runs to its end: the condition is only in the data)."""
+    cfg = inputs.config("c1", **{"mesh.n": 2, "mesh.perturb": 0.1, "pml.lo": [-1.0] * 3, "pml.hi": [1.0] * 3})
+    _say(f"watchdog beyond the stability bound, precision {precision}")
+    sim, osim = _pair(wdg, cfg, precision=precision, init="random", seed=7)
+    e0 = sim.energy()
+    sim.step(osim.dt, 30)
+    osim.run(30)
+    assert _rel_l2(sim.get_fields(), osim.q) <= (1e-12 if precision == 0 else 1e-5)
+    assert sim.energy() <= e0
+    code = None
+    for _ in range(40):
+        sim.step(50 * osim.dt, 5)
+        try:
+            sim.energy()
+        except wdg.WdgError as e:
+            code = e.code
+            break
+    assert code == wdg.WDG_ENONFINITE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_stale_residual_is_not_read(wdg, precision, kernel):
     """The first LSERK stage (A_1 = 0) and the right-hand side must not read the residual

@@ -69,3 +69,37 @@ def test_fourth_order():
         errs.append(abs(float(y) - exact(2.0)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(np.abs(rates - 4.0) < 0.25), rates
+
+
+def test_cavity_energy_under_the_dt_rule_and_blow_up_beyond_it():
+    """A vacuum PEC cavity with the upwind flux: the semi-discrete energy does not grow, so LSERK4 at the recipes'
+    dt rule (inside its stability region) keeps the energy at or below its start and the upwind flux dissipates
+    some of it; fifty times that step leaves the region and the energy grows until it is no longer finite, the
+    condition the library's energy readout reports as WDG_ENONFINITE."""
+    from oracle.run import Simulation
+    from paper_2006_02551_amd import inputs
+
+    cfg = inputs.config("c1", **{"mesh.n": 2, "mesh.perturb": 0.1, "pml.lo": [-1.0] * 3, "pml.hi": [1.0] * 3})
+    vx, ev = inputs.mesh_for(cfg)
+    rst, w = inputs.load_rule(cfg["cub_degree"])
+    q0 = np.random.default_rng(7).standard_normal((ev.shape[0], 12, (cfg["N"] + 1) * (cfg["N"] + 2) * (cfg["N"] + 3) // 6))
+    sim = Simulation(cfg, vx, ev, rst, w)
+    assert not sim.op.is_pml.any()
+    sim.set_state(q0)
+    e = [sim.energy()]
+    for _ in range(30):
+        sim.run(1)
+        e.append(sim.energy())
+    assert max(e) <= e[0] * (1 + 1e-12)
+    assert e[-1] < 0.9 * e[0]
+
+    big = Simulation(cfg, vx, ev, rst, w)
+    big.set_state(q0)
+    with np.errstate(over="ignore", invalid="ignore"):
+        big.run(3, dt=50 * sim.dt)
+        assert big.energy() > 1e6 * e[0]
+        for _ in range(200):
+            big.run(1, dt=50 * sim.dt)
+            if not np.isfinite(big.energy()):
+                break
+        assert not np.isfinite(big.energy())
