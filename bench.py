@@ -257,7 +257,7 @@ def run_adjoint(precision):
             "dJ_dsigma_max": list(gp[:3]), "dJ_dL": list(gp[3:6]), "dJ_dorder": gp[6]}
 
 
-def run_batch(steps, warmup, seq_steps=50, group_mb=128.0):
+def run_batch(steps, warmup, seq_steps=50, group_mb=256.0):
     """The batching form: 32 independent simulations (8^3 x 6 .. 24^3 x 6 tets, 1,282,008 in all, N=3, each
     with its own sigma profile and time step) stepped in one context in FP32 with captured two-step graphs,
     against the same simulations stepped one after another, each in a context of its own."""
@@ -287,7 +287,8 @@ def run_batch(steps, warmup, seq_steps=50, group_mb=128.0):
     dofs = d.K * d.Np
     del b.sim
     # the same batch with cache-sized step groups (aligned components, both steps of a captured pair group
-    # after group)
+    # after group); groups of about 256 MB of fields and setup data were the fastest of 32-384 MB
+    # (3.52e9 DOF/s against 3.39e9 at 128 MB and 3.02e9 ungrouped)
     gb = Batch(cfg, wdg.WDG_FP32, group_mb=group_mb)
     gb.sim.set_kernel(wdg.WDG_KERNEL_MFMA if chosen["kernel"] == "mfma" else wdg.WDG_KERNEL_SCALAR)
     if chosen["kernel"] == "mfma":

@@ -3,8 +3,8 @@
 //  - the shell energy 1/2 sum_k J_k sum_q w_q chi (V_q u)^2 (cubature form,
 //    eqs. (19)-(20)) and its energy-inner-product gradient P_q (chi V_q u).
 // One workgroup per 64-element block, wavefront u = field component u, lane =
-// element slot; the operators V_q and P_q^T are staged in LDS and read as
-// wave-uniform operands.
+// element slot; the operators V_q and P_q^T and the block's shell indicator
+// are staged in LDS (operators read as wave-uniform operands).
 #include "device.hpp"
 
 namespace wdg {
@@ -17,25 +17,40 @@ struct OrdA {
     static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
 };
 
-template <typename real, int N>
+// Dynamic LDS of the shell kernels: V_q (and P_q^T) [Nq][Np], then, when CL, the block's shell indicator
+// [Nq][B] (staged with the operators, so the cubature loop waits for no global load).
+template <typename real>
+constexpr size_t shell_lds(int Nq, int Np, int nops, bool cl) {
+    return (static_cast<size_t>(nops) * Nq * Np + (cl ? static_cast<size_t>(Nq) * kBlock : 0)) * sizeof(real);
+}
+constexpr size_t kShellLdsMax = 64 * 1024;
+
+template <typename real, int N, bool CL>
 __global__ __launch_bounds__(kThreads) void shell_energy_kernel(ShellParams p) {
     constexpr int Np = OrdA<N>::Np, B = kBlock, EHS = 6 * Np * B;
-    __shared__ real sV[kQmax * Np];
+    extern __shared__ __attribute__((aligned(16))) char dyn[];
+    real* sV = reinterpret_cast<real*>(dyn);
+    real* sC = sV + p.Nq * Np;
     __shared__ double red[kThreads];
     const int Nq = p.Nq, sb = static_cast<int>(blockIdx.x), tid = static_cast<int>(threadIdx.x);
     const int u = tid >> 6, lane = tid & 63;
+    const real* chig = static_cast<const real*>(p.chi) + static_cast<size_t>(sb) * Nq * B;
     for (int i = tid; i < Nq * Np; i += kThreads) sV[i] = static_cast<const real*>(p.Vq)[i];
-    __syncthreads();
+    if (CL)
+        for (int i = tid; i < Nq * B; i += kThreads) sC[i] = chig[i];
     const int blk = p.blocks[sb];
     const real* q = static_cast<const real*>(p.q) + static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
     real uv[Np];
 #pragma unroll
     for (int i = 0; i < Np; ++i) uv[i] = q[static_cast<size_t>(i) * B];
-    const real* chi = static_cast<const real*>(p.chi) + static_cast<size_t>(sb) * Nq * B + lane;
     const double J = p.Jk[static_cast<size_t>(blk) * B + lane];
+    __syncthreads();
+    const real* chi;
+    if constexpr (CL) chi = sC + lane;
+    else chi = chig + lane;
     double acc = 0.0;
     for (int qq = 0; qq < Nq; ++qq) {
-        const real c = chi[static_cast<size_t>(qq) * B];
+        const real c = chi[qq * B];
         real v = real(0);
 #pragma unroll
         for (int jj = 0; jj < Np; ++jj) v += sV[qq * Np + jj] * uv[jj];
@@ -65,17 +80,22 @@ __global__ __launch_bounds__(256) void sum_into_kernel(const double* partial, in
     if (tid == 0) *acc += scale * red[0];
 }
 
-template <typename real, int N>
+template <typename real, int N, bool CL>
 __global__ __launch_bounds__(kThreads) void shell_inject_kernel(ShellParams p) {
     constexpr int Np = OrdA<N>::Np, B = kBlock, EHS = 6 * Np * B;
-    __shared__ real sV[kQmax * Np], sP[kQmax * Np];
+    extern __shared__ __attribute__((aligned(16))) char dyn[];
+    real* sV = reinterpret_cast<real*>(dyn);
+    real* sP = sV + p.Nq * Np;
+    real* sC = sP + p.Nq * Np;
     const int Nq = p.Nq, sb = static_cast<int>(blockIdx.x), tid = static_cast<int>(threadIdx.x);
     const int u = tid >> 6, lane = tid & 63;
+    const real* chig = static_cast<const real*>(p.chi) + static_cast<size_t>(sb) * Nq * B;
     for (int i = tid; i < Nq * Np; i += kThreads) {
         sV[i] = static_cast<const real*>(p.Vq)[i];
         sP[i] = static_cast<const real*>(p.PqT)[i];
     }
-    __syncthreads();
+    if (CL)
+        for (int i = tid; i < Nq * B; i += kThreads) sC[i] = chig[i];
     const int blk = p.blocks[sb];
     const size_t off = static_cast<size_t>(blk) * EHS + static_cast<size_t>(u) * Np * B + lane;
     const real* q = static_cast<const real*>(p.q) + off;
@@ -86,9 +106,12 @@ __global__ __launch_bounds__(kThreads) void shell_inject_kernel(ShellParams p) {
         uv[i] = q[static_cast<size_t>(i) * B];
         gv[i] = real(0);
     }
-    const real* chi = static_cast<const real*>(p.chi) + static_cast<size_t>(sb) * Nq * B + lane;
+    __syncthreads();
+    const real* chi;
+    if constexpr (CL) chi = sC + lane;
+    else chi = chig + lane;
     for (int qq = 0; qq < Nq; ++qq) {
-        const real c = chi[static_cast<size_t>(qq) * B];
+        const real c = chi[qq * B];
         real v = real(0);
 #pragma unroll
         for (int jj = 0; jj < Np; ++jj) v += sV[qq * Np + jj] * uv[jj];
@@ -101,30 +124,34 @@ __global__ __launch_bounds__(kThreads) void shell_inject_kernel(ShellParams p) {
     for (int i = 0; i < Np; ++i) qh[static_cast<size_t>(i) * B] += dt * gv[i];
 }
 
-template <typename real>
-int energy_n(int N, const ShellParams& p, hipStream_t s) {
+template <typename real, int N>
+int shell_launch(bool inject, const ShellParams& p, hipStream_t s) {
+    constexpr int Np = OrdA<N>::Np;
+    const int nops = inject ? 2 : 1;
     const dim3 g(p.nsb), b(kThreads);
-    switch (N) {
-        case 1: hipLaunchKernelGGL((shell_energy_kernel<real, 1>), g, b, 0, s, p); break;
-        case 2: hipLaunchKernelGGL((shell_energy_kernel<real, 2>), g, b, 0, s, p); break;
-        case 3: hipLaunchKernelGGL((shell_energy_kernel<real, 3>), g, b, 0, s, p); break;
-        case 4: hipLaunchKernelGGL((shell_energy_kernel<real, 4>), g, b, 0, s, p); break;
-        default: return static_cast<int>(hipErrorInvalidValue);
+    // the indicator goes to LDS with the operators wherever both fit in the default 64 KiB
+    const bool cl = shell_lds<real>(p.Nq, Np, nops, true) <= kShellLdsMax;
+    const size_t lds = shell_lds<real>(p.Nq, Np, nops, cl);
+    if (lds > kShellLdsMax) return static_cast<int>(hipErrorInvalidValue);
+    if (inject) {
+        if (cl) hipLaunchKernelGGL((shell_inject_kernel<real, N, true>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((shell_inject_kernel<real, N, false>), g, b, lds, s, p);
+    } else {
+        if (cl) hipLaunchKernelGGL((shell_energy_kernel<real, N, true>), g, b, lds, s, p);
+        else hipLaunchKernelGGL((shell_energy_kernel<real, N, false>), g, b, lds, s, p);
     }
     return static_cast<int>(hipGetLastError());
 }
 
 template <typename real>
-int inject_n(int N, const ShellParams& p, hipStream_t s) {
-    const dim3 g(p.nsb), b(kThreads);
+int shell_n(int N, bool inject, const ShellParams& p, hipStream_t s) {
     switch (N) {
-        case 1: hipLaunchKernelGGL((shell_inject_kernel<real, 1>), g, b, 0, s, p); break;
-        case 2: hipLaunchKernelGGL((shell_inject_kernel<real, 2>), g, b, 0, s, p); break;
-        case 3: hipLaunchKernelGGL((shell_inject_kernel<real, 3>), g, b, 0, s, p); break;
-        case 4: hipLaunchKernelGGL((shell_inject_kernel<real, 4>), g, b, 0, s, p); break;
+        case 1: return shell_launch<real, 1>(inject, p, s);
+        case 2: return shell_launch<real, 2>(inject, p, s);
+        case 3: return shell_launch<real, 3>(inject, p, s);
+        case 4: return shell_launch<real, 4>(inject, p, s);
         default: return static_cast<int>(hipErrorInvalidValue);
     }
-    return static_cast<int>(hipGetLastError());
 }
 
 }  // namespace
@@ -132,7 +159,7 @@ int inject_n(int N, const ShellParams& p, hipStream_t s) {
 int launch_shell_energy(int precision, int N, const ShellParams& p, hipStream_t s) {
     if (p.Nq > kQmax) return static_cast<int>(hipErrorInvalidValue);
     if (p.nsb == 0) return 0;
-    return precision == 0 ? energy_n<double>(N, p, s) : energy_n<float>(N, p, s);
+    return precision == 0 ? shell_n<double>(N, false, p, s) : shell_n<float>(N, false, p, s);
 }
 
 int launch_sum_into(const double* partial, int n, double scale, double* acc, hipStream_t s) {
@@ -143,7 +170,7 @@ int launch_sum_into(const double* partial, int n, double scale, double* acc, hip
 int launch_shell_inject(int precision, int N, const ShellParams& p, hipStream_t s) {
     if (p.Nq > kQmax) return static_cast<int>(hipErrorInvalidValue);
     if (p.nsb == 0) return 0;
-    return precision == 0 ? inject_n<double>(N, p, s) : inject_n<float>(N, p, s);
+    return precision == 0 ? shell_n<double>(N, true, p, s) : shell_n<float>(N, true, p, s);
 }
 
 }  // namespace wdg
