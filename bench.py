@@ -54,11 +54,11 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 # Taken on the kernel sources with this sha256 (kernels_mfma.hip + device.hpp); reported only while they are
 # unchanged.
 MEASURED_TRAFFIC = {
-    "source_sha256": "0ba3f8879da7140b2df9fd54152bbc2e0aaae40b11d61b894b6e5f795b16a370",
-    "stage_mfma_kernel<double,N=3,Nq=24>": {"read": (179176390, 265403898), "write": (164413440, 164413440)},
-    "stage_mfma_kernel<float,N=3,Nq=24>": {"read": (87836256, 131307286), "write": (90165376, 91789517)},
-    "stage_mfma_kernel<double,N=4,Nq=51>": {"read": (2579232174, 3781003632), "write": (2226524160, 2226524160)},
-    "stage_mfma_kernel<float,N=4,Nq=51>": {"read": (1278044270, 1906668094), "write": (1178140069, 1252153093)},
+    "source_sha256": "6c81e2c97b12f92b0f091a2498830f7d419e1a7135fc7a4fd62d26d69bfd117d",
+    "stage_mfma_kernel<double,N=3,Nq=24>": {"read": (179073427, 265663581), "write": (164413440, 164413440)},
+    "stage_mfma_kernel<float,N=3,Nq=24>": {"read": (87843738, 131361021), "write": (90011091, 91748061)},
+    "stage_mfma_kernel<double,N=4,Nq=51>": {"read": (2577386597, 3780726158), "write": (2226524160, 2226524160)},
+    "stage_mfma_kernel<float,N=4,Nq=51>": {"read": (1283326894, 1906585237), "write": (1176534107, 1252422759)},
 }
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)

@@ -24,8 +24,9 @@
 // operator compact, see device.hpp), copied once per workgroup into LDS and
 // read with one 64-lane LDS load per fragment.  Field data are the B
 // operands.  The upwind flux of all six components is computed once per tile
-// by its 384 threads (one face node and element per thread) and shared
-// through LDS, in two rounds of half the face nodes each.
+// by its 384 threads (face node and element items) and shared through LDS, in
+// one round, or in two rounds of half the face nodes each where the LDS of a
+// compute unit is short.
 //
 // Register chaining.  Lane l = 16 g + j holds column j; an MFMA result keeps
 // four values per lane (register v).  The host permutes the rows of every
