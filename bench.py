@@ -31,7 +31,6 @@ FP32).
 
 Usage: python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline] [--stepping-only]
                        [--table-i-only | --adjoint-only | --precision-form-only [--pf-steps K] | --batch-only]
-                       [--copy-calibration MIB]
 """
 from __future__ import annotations
 
@@ -512,9 +511,6 @@ def main():
                     help="timed steps of the precision-form leg (e.g. fewer under a counter profiler)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run the 32-simulation batching leg only and print its JSON (e.g. under a profiler)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="first run a plain device copy of MIB MiB three times (a known-size reference for "
-                         "hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the element-partitioned "
@@ -526,15 +522,6 @@ def main():
     from paper_2006_02551_amd import inputs, wdg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"bench: copied {args.copy_calibration} MiB three times", file=sys.stderr, flush=True)
-        del src, dst
     if args.table_i_only:
         print(json.dumps({"table_i": run_table_i()}))
         return
