@@ -77,6 +77,29 @@ def test_shell_energy_matches_oracle(wdg):
         assert ref > 0 and abs(got - ref) <= tol * ref, (precision, got, ref)
 
 
+def test_shell_energy_with_a_large_rule(wdg):
+    """A 125-point rule at N = 3: in FP64 the block's shell indicator does not fit in the shell kernel's LDS beside
+    V_q and is read from global memory inside the cubature loop; in FP32 it is staged."""
+    from oracle import adjoint as A
+    from oracle.run import Simulation as OSim
+    cfg = inputs.config("c1", **{"N": 3, "mesh.n": 3, "mesh.perturb": 0.1, "init.width": 0.35})
+    rule = inputs.product_rule(5)
+    assert len(rule[1]) == 125
+    vx, ev = inputs.mesh_for(cfg)
+    osim = OSim(cfg, vx, ev, *rule)
+    q0 = inputs.gaussian_fields(cfg, osim.mesh.x)
+    q0[:, 0:6] += 0.05 * np.random.default_rng(3).standard_normal(q0[:, 0:6].shape)
+    osim.set_state(q0)
+    chi = A.shell_weights(osim.op, SHELL_C1)
+    ref = A.shell_energy(osim.op, chi, osim.q)
+    _say("shell energy, 125-point rule")
+    for precision, tol in ((0, 1e-13), (1, 1e-6)):
+        sim = wdg.Simulation(vx, ev, cfg["N"], rule, cfg["pml"], cfg["alpha"], precision)
+        sim.set_fields(q0)
+        got = sim.shell_energy(SHELL_C1)
+        assert ref > 0 and abs(got - ref) <= tol * ref, (precision, got, ref)
+
+
 @pytest.mark.parametrize("name,over,nsteps", [
     ("c1", {"mesh.perturb": 0.1, "init.width": 0.35}, 12),            # N = 2, quadratic profile
     ("c2", {"mesh.n": 5, "init": {"component": 2, "center": [0.0] * 3, "width": 0.5}}, 8),  # N = 3, cubic, dipole
