@@ -53,11 +53,11 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 # Taken on the kernel sources with this sha256 (kernels_mfma.hip + device.hpp); reported only while they are
 # unchanged.
 MEASURED_TRAFFIC = {
-    "source_sha256": "6c81e2c97b12f92b0f091a2498830f7d419e1a7135fc7a4fd62d26d69bfd117d",
-    "stage_mfma_kernel<double,N=3,Nq=24>": {"read": (179073427, 265663581), "write": (164413440, 164413440)},
-    "stage_mfma_kernel<float,N=3,Nq=24>": {"read": (87843738, 131361021), "write": (90011091, 91748061)},
-    "stage_mfma_kernel<double,N=4,Nq=51>": {"read": (2577386597, 3780726158), "write": (2226524160, 2226524160)},
-    "stage_mfma_kernel<float,N=4,Nq=51>": {"read": (1283326894, 1906585237), "write": (1176534107, 1252422759)},
+    "source_sha256": "ddf702916dadfc80c9b5ef40f1c14375df0cccc1f44252a87918d26e3b1cc2c0",
+    "stage_mfma_kernel<double,N=3,Nq=24>": {"read": (178197248, 264747651), "write": (164413440, 164413440)},
+    "stage_mfma_kernel<float,N=3,Nq=24>": {"read": (87352160, 130684352), "write": (89520294, 91302426)},
+    "stage_mfma_kernel<double,N=4,Nq=51>": {"read": (2583748462, 3789409410), "write": (2226524160, 2226524160)},
+    "stage_mfma_kernel<float,N=4,Nq=51>": {"read": (1287543653, 1920225666), "write": (1175017728, 1253561611)},
 }
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 (packed vector / matrix)

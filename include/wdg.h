@@ -282,12 +282,19 @@ int32_t wdg_autotune_cached(wdg_ctx* ctx, int32_t reps, void* hip_stream, int32_
  * amplitude and the probe row change every step. */
 int32_t wdg_step_graph(wdg_ctx* ctx, double dt, int32_t nsteps, void* hip_stream);
 
+#define WDG_SCHEDULE_FORWARD 0
+#define WDG_SCHEDULE_REVERSED 1
+#define WDG_SCHEDULE_ALTERNATING 2 /* the default */
 /* Order in which workgroups take the element tiles (blocks) of a stage launch:
- * 0 natural (default), 1 reversed.  Every element's stage arithmetic reads
- * only q_in and writes only its own rows of q_out and the residual (ping-pong
- * buffers), so the results must be bitwise identical in either order: a
- * check for cross-element read-after-write hazards.  WDG_EINVAL otherwise. */
-int32_t wdg_set_schedule(wdg_ctx* ctx, int32_t reversed);
+ * WDG_SCHEDULE_FORWARD (natural order), WDG_SCHEDULE_REVERSED, or
+ * WDG_SCHEDULE_ALTERNATING (the default: successive stage launches alternate
+ * between the two, so that a stage starts on the rows the previous one wrote
+ * last, which are the ones still in the last-level cache when the state is
+ * somewhat larger than it).  Every element's stage arithmetic reads only q_in
+ * and writes only its own rows of q_out and the residual (ping-pong buffers),
+ * so the results are bitwise identical in every order: a check for
+ * cross-element read-after-write hazards.  WDG_EINVAL for another mode. */
+int32_t wdg_set_schedule(wdg_ctx* ctx, int32_t mode);
 
 /* The weight-adjusted inverse P_q a^-1 V_q of eq. (21) is applied to every PML
  * element's right-hand side by default, also where it is the identity: with

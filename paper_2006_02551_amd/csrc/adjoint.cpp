@@ -125,7 +125,7 @@ int adjoint_stage(wdg_ctx* c, const void* z, const void* y, const void* qhat_in,
     p.nint = S.nblk - S.nblk_pml;
     p.Nq = S.ref.Nq;
     p.read_res = 1;
-    p.order_rev = c->order_rev ? 1 : 0;
+    p.order_rev = c->next_order_rev();
     p.rk_a = 0.0;
     p.rk_b = 0.0;
     p.dt = dt;

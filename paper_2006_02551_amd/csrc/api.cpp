@@ -278,7 +278,7 @@ int launch_stage_on(wdg_ctx* c, const void* qin, void* qout, void* res, double r
     }
     p.Nq = S.ref.Nq;
     p.read_res = read_res ? 1 : 0;
-    p.order_rev = c->order_rev ? 1 : 0;
+    p.order_rev = c->next_order_rev();
     p.rk_a = rk_a;
     p.rk_b = rk_b;
     p.dt = dt;

@@ -179,10 +179,12 @@ int32_t wdg_set_step_groups(wdg_ctx* c, int32_t ngroups, const int32_t* group) {
     });
 }
 
-int32_t wdg_set_schedule(wdg_ctx* c, int32_t reversed) {
-    if (!c || (reversed != 0 && reversed != 1)) return WDG_EINVAL;
+int32_t wdg_set_schedule(wdg_ctx* c, int32_t mode) {
+    if (!c || (mode != WDG_SCHEDULE_FORWARD && mode != WDG_SCHEDULE_REVERSED && mode != WDG_SCHEDULE_ALTERNATING))
+        return WDG_EINVAL;
     c->drop_graph();
-    c->order_rev = reversed != 0;
+    c->schedule = mode;
+    c->sweep_count = 0;
     return WDG_OK;
 }
 

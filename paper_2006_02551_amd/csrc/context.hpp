@@ -84,7 +84,13 @@ struct wdg_ctx {
     bool mfma_ok = false;
     bool waa_identity = false;  // kappa = 1 and P_q V_q = I to rounding
     bool waa_skip = false;      // skip the weight-adjusted inverse (only where waa_identity holds; opt-in)
-    bool order_rev = false;     // workgroups take tiles in reversed order (schedule-permutation check)
+    int schedule = WDG_SCHEDULE_ALTERNATING;  // order in which workgroups take the tiles (wdg_set_schedule)
+    uint64_t sweep_count = 0;                  // stage launches made with the alternating schedule
+    // reversed order for the next stage launch (advances the alternating schedule)
+    int next_order_rev() {
+        if (schedule == WDG_SCHEDULE_ALTERNATING) return static_cast<int>(sweep_count++ & 1);
+        return schedule == WDG_SCHEDULE_REVERSED ? 1 : 0;
+    }
     // step groups (aligned layouts only): per group [pml0, npml, int0, nint] block ranges; stage launches
     // cover range while range_on
     std::vector<std::array<int, 4>> groups;

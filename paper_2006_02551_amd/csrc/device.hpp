@@ -111,7 +111,7 @@ struct StageParams {
     // applies P_q a^-1 V_q on every PML element
     int waa_skip;
     int read_res;         // 0 when the Runge-Kutta coefficient A is zero
-    int order_rev;        // 1: workgroups take their tiles / blocks in reversed order (schedule-permutation check)
+    int order_rev;        // 1: workgroups take their tiles / blocks in reversed order (wdg_set_schedule)
     // blocks this launch covers: [pml0, pml0 + npml) of the PML class and [int0, int0 + nint) of the vacuum
     // class (every block unless a launch is restricted to a group of independent simulations)
     int pml0, npml, int0, nint;

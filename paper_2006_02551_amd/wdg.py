@@ -38,6 +38,7 @@ WDG_HOST_ONLY = 1
 WDG_ALIGN_COMPONENTS = 2
 WDG_OP_DR, WDG_OP_DS, WDG_OP_DT, WDG_OP_LIFT, WDG_OP_VQ, WDG_OP_PQ, WDG_OP_M = range(7)
 WDG_KERNEL_AUTO, WDG_KERNEL_SCALAR, WDG_KERNEL_MFMA = 0, 1, 2
+WDG_SCHEDULE_FORWARD, WDG_SCHEDULE_REVERSED, WDG_SCHEDULE_ALTERNATING = 0, 1, 2
 WDG_PML_WAA, WDG_PML_DIRECT, WDG_PML_CONSTANT = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -382,8 +383,9 @@ class Simulation(Context):
         n = int(g.max()) + 1 if ngroups is None else int(ngroups)
         _check(wdg_set_step_groups(self.h, n, g.ctypes.data_as(C.POINTER(C.c_int32))), self.h)
 
-    def set_schedule(self, reversed_order):
-        _check(wdg_set_schedule(self.h, int(bool(reversed_order))), self.h)
+    def set_schedule(self, mode):
+        """WDG_SCHEDULE_FORWARD, WDG_SCHEDULE_REVERSED or WDG_SCHEDULE_ALTERNATING (the default)."""
+        _check(wdg_set_schedule(self.h, int(mode)), self.h)
 
     def set_waa_shortcut(self, on):
         """Skip (True) or apply (False, the default) the weight-adjusted inverse where it is the identity."""

@@ -140,20 +140,21 @@ def test_loss_and_gradient_fp32_against_fp64_oracle(wdg, name, over, nsteps):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_adjoint_schedule_permutation(wdg, precision):
-    # reversed tile order: the loss and the final state bitwise equal; the sigma gradient (LDS atomic sums
-    # in no fixed order) to rounding
+    # natural, reversed and alternating tile order: the loss and the final state bitwise equal; the sigma
+    # gradient (LDS atomic sums in no fixed order) to rounding
     cfg = inputs.config("c1", **{"mesh.perturb": 0.1, "init.width": 0.35})
     _say(f"adjoint schedule permutation, precision {precision}")
     res = []
-    for rev in (0, 1):
+    for mode in (wdg.WDG_SCHEDULE_FORWARD, wdg.WDG_SCHEDULE_REVERSED, wdg.WDG_SCHEDULE_ALTERNATING):
         sim, osim, q0 = _pair(wdg, cfg, precision)
-        sim.set_schedule(rev)
+        sim.set_schedule(mode)
         J, g, gp = sim.loss_gradient(osim.dt, 10, SHELL_C1)
         res.append((J, g, sim.get_fields()))
-    assert res[0][0] == res[1][0]
-    assert np.array_equal(res[0][2], res[1][2])
     tol = 1e-12 if precision == 0 else 1e-5
-    assert np.max(np.abs(res[0][1] - res[1][1])) <= tol * np.max(np.abs(res[0][1]))
+    for r in res[1:]:
+        assert r[0] == res[0][0]
+        assert np.array_equal(r[2], res[0][2])
+        assert np.max(np.abs(r[1] - res[0][1])) <= tol * np.max(np.abs(res[0][1]))
 
 
 def test_checkpoint_interval_and_empty_shell(wdg):

@@ -257,26 +257,30 @@ def test_determinism_and_restart(wdg):
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_schedule_permutation_is_bitwise_neutral(wdg, precision, kernel):
-    """Workgroups taking the tiles in reversed order give bitwise-identical states (no cross-element
-    read-after-write hazard: each stage reads q_in and writes its own rows of q_out and the residual)."""
+    """Workgroups taking the tiles in natural, reversed or alternating order (the default) give bitwise-identical
+    states (no cross-element read-after-write hazard: each stage reads q_in and writes its own rows of q_out and
+    the residual)."""
     cfg = inputs.config("c2", **{"mesh.n": 6})
     _say(f"schedule permutation: precision {precision} kernel {kernel}")
+    modes = (wdg.WDG_SCHEDULE_FORWARD, wdg.WDG_SCHEDULE_REVERSED, wdg.WDG_SCHEDULE_ALTERNATING)
     out = []
-    for rev in (0, 1):
+    for mode in modes:
         sim, osim = _pair(wdg, cfg, precision=precision, kernel=kernel)
-        sim.set_schedule(rev)
+        sim.set_schedule(mode)
         sim.step(osim.dt, 12)
         out.append(sim.get_fields())
-    assert np.array_equal(out[0], out[1])
+    assert all(np.array_equal(out[0], o) for o in out[1:])
     if kernel == 0:  # the direct scheme's second launch too
         out = []
-        for rev in (0, 1):
+        for mode in modes:
             sim, osim = _pair(wdg, cfg, precision=precision, kernel=kernel)
             sim.set_pml_scheme(wdg.WDG_PML_DIRECT, inputs.product_rule(5))
-            sim.set_schedule(rev)
+            sim.set_schedule(mode)
             sim.step(osim.dt, 4)
             out.append(sim.get_fields())
-        assert np.array_equal(out[0], out[1])
+        assert all(np.array_equal(out[0], o) for o in out[1:])
+    with pytest.raises(wdg.WdgError):
+        sim.set_schedule(3)
 
 
 def test_edge_cases(wdg):

@@ -108,6 +108,11 @@ def test_error_paths():
     ctx = wdg.Context(vx, ev, 2, rule, cfg["pml"], host_only=True)
     assert wdg.wdg_step(ctx.h, 0.01, 1, None) == wdg.WDG_ESTATE
     assert wdg.wdg_bind_state(ctx.h, None, None, None, 0) == wdg.WDG_ESTATE
+    # schedule modes: forward, reversed, alternating (the default); nothing else
+    for mode in (wdg.WDG_SCHEDULE_FORWARD, wdg.WDG_SCHEDULE_REVERSED, wdg.WDG_SCHEDULE_ALTERNATING):
+        assert wdg.wdg_set_schedule(ctx.h, mode) == 0
+    assert wdg.wdg_set_schedule(ctx.h, 3) == wdg.WDG_EINVAL
+    assert wdg.wdg_set_schedule(ctx.h, -1) == wdg.WDG_EINVAL
 
 
 def test_negative_orientation_is_swapped_like_the_oracle():
